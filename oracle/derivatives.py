@@ -1,0 +1,241 @@
+"""Implicit derivatives of one step and of a rollout, in FP64.
+
+Follows the paper's "Differentiating Through Simulation" paragraph:
+
+* stage 1: dq*/dtheta = -(dF/dq*)^{-1} dF/dtheta;
+* stage 2: dq+/dq* = -[I 0] K^{-1} dG/dq*, K the KKT matrix;
+* eq. (diff-sim): the adjoint solves with K^T, applies the VJP of dG/dq*,
+  solves with (dF/dq*)^T and applies the VJP of dF/dtheta.
+
+Written out for this model (free DoFs f, gripped DoFs g, b = gripper
+targets, H = dF/dy at y*, which is also the stage-2 matrix P):
+
+  W = d^3E[D] (third derivative contracted with the stage-2 correction D)
+  C = sum_c lam_c d^2 phi_c        (SDF curvature, block-diagonal)
+  smoothed (kappa > 0), with Lam = diag(kappa / gap^2):
+    K = P + N^T Lam N,   R = sum_c (kappa/gap_c^2) n_c (d^2 phi_c D_p)^T
+    dx+_f = K^{-1} [ (P - W_ff + C - R) dy_f - W_fg db ]
+  hard (kappa = 0), active set A:
+    [[P, -N_A^T], [N_A, 0]] [dD; dlam] = -[ (W_ff - C) dy_f + W_fg db ; (N_A + R_A) dy_f ]
+    with R_A rows (d^2 phi_c D_p)^T,   dx+_f = dy_f + dD
+  stage 1: H_ff dy_f = (M/dt^2) dxhat_f - H_fg db,
+           dxhat = dx + dt (1 - gamma) dv,   db = dx_g + dt du
+  output:  dv+_f = (dx+_f - dx_f)/dt,  dx+_g = db,  dv+_g = du.
+
+Every product above is a plain sparse matrix product; every inverse is a
+sparse LU solve.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import model
+from .step import Layout, normal_matrix, psi_hessian_ff, rollout, step
+
+
+def _blockdiag(lay, pair_node, mats):
+    """Sum of per-pair 3x3 blocks placed on the diagonal block of their node."""
+    nf = len(lay.free_nodes)
+    if len(pair_node) == 0:
+        return sp.csr_matrix((3 * nf, 3 * nf))
+    ii, jj = np.meshgrid(np.arange(3), np.arange(3), indexing="ij")
+    base = 3 * lay.fpos[pair_node]
+    rows = (base[:, None, None] + ii[None]).ravel()
+    cols = (base[:, None, None] + jj[None]).ravel()
+    return sp.coo_matrix((mats.ravel(), (rows, cols)), shape=(3 * nf, 3 * nf)).tocsr()
+
+
+class StepDerivative:
+    """Linearisation of f_kappa at (s, u): JVP, VJP and dense A, B."""
+
+    def __init__(self, inst, s, u_t, kappa, el=None, lay=None):
+        self.inst = inst
+        self.el = model.elements(inst) if el is None else el
+        self.lay = Layout(inst) if lay is None else lay
+        n = inst.n
+        self.n = n
+        s = np.asarray(s, dtype=np.float64)
+        self.x = s[:3 * n].reshape(n, 3)
+        self.v = s[3 * n:].reshape(n, 3)
+        self.res = r = step(inst, self.x, self.v, u_t, kappa, self.el, self.lay)
+        self.kappa = kappa
+        lay = self.lay
+        fi, gi = lay.fidx, lay.gidx
+        Hfull = model.hessian(self.el, r.y)
+        self.Hff = psi_hessian_ff(inst, self.el, lay, r.y, project=False)
+        self.Hfg = Hfull[fi][:, gi].tocsr()
+        Wfull = model.third(self.el, r.y, r.delta)
+        self.Wff = Wfull[fi][:, fi].tocsr()
+        self.Wfg = Wfull[fi][:, gi].tocsr()
+        N = normal_matrix(lay, r.pair_node, r.normal)
+        self.C = _blockdiag(lay, r.pair_node, r.lam[:, None, None] * r.curv)
+        dp = r.delta[r.pair_node]                                   # (nc, 3)
+        hd = np.einsum("cij,cj->ci", r.curv, dp)                    # d^2 phi D_p
+        self.Hlu = spla.splu(self.Hff)
+        if kappa > 0.0:
+            w = kappa / r.gap ** 2
+            self.R = _blockdiag(lay, r.pair_node, w[:, None, None] * r.normal[:, :, None] * hd[:, None, :])
+            self.K = (self.Hff + N.T @ sp.diags(w) @ N).tocsc()
+            self.Klu = spla.splu(self.K)
+            self.J = (self.Hff - self.Wff + self.C - self.R).tocsr()
+        else:
+            act = r.active
+            NA = N[act]
+            nc = len(r.pair_node)
+            RA = sp.csr_matrix((hd.ravel(), (np.repeat(np.arange(nc), 3),
+                                             (3 * lay.fpos[r.pair_node][:, None] + np.arange(3)[None]).ravel())),
+                               shape=(nc, N.shape[1]))[act]
+            self.NA, self.RA = NA.tocsr(), RA.tocsr()
+            na = NA.shape[0]
+            Kk = np.block([[self.Hff.toarray(), -NA.toarray().T], [NA.toarray(), np.zeros((na, na))]])
+            self.Kkkt = Kk
+            self.nA = na
+
+    # ------------------------------------------------------------------ JVP
+    def jvp(self, dx, dv, du):
+        """Tangents (3n, m), (3n, m), (n_u, m) -> (dx+, dv+), each (3n, m)."""
+        inst, lay = self.inst, self.lay
+        dt, gam = inst.dt, inst.gamma
+        dx = np.asarray(dx, dtype=np.float64)
+        dv = np.asarray(dv, dtype=np.float64)
+        du = np.asarray(du, dtype=np.float64)
+        if dx.ndim == 1:
+            dx, dv, du = dx[:, None], dv[:, None], du[:, None]
+        m = dx.shape[1]
+        db = np.zeros_like(dx)
+        for k, j in enumerate(inst.grip_nodes):
+            db[3 * j:3 * j + 3] = dx[3 * j:3 * j + 3] + dt * du[3 * k:3 * k + 3]
+        fi, gi = lay.fidx, lay.gidx
+        dxhat_f = dx[fi] + dt * (1.0 - gam) * dv[fi]
+        rhs1 = inst.mass / dt ** 2 * dxhat_f - self.Hfg @ db[gi]
+        dy_f = self.Hlu.solve(rhs1)
+        if self.kappa > 0.0:
+            dxn_f = self.Klu.solve(self.J @ dy_f - self.Wfg @ db[gi])
+        else:
+            top = -((self.Wff - self.C) @ dy_f + self.Wfg @ db[gi])
+            bot = -((self.NA + self.RA) @ dy_f) if self.nA else np.zeros((0, m))
+            sol = np.linalg.solve(self.Kkkt, np.vstack([top, bot])) if self.nA else \
+                np.linalg.solve(self.Kkkt, top)
+            dxn_f = dy_f + sol[:len(fi)]
+        dxn = db.copy()
+        dxn[fi] = dxn_f
+        dvn = (dxn - dx) / dt
+        for k, j in enumerate(inst.grip_nodes):
+            dvn[3 * j:3 * j + 3] = du[3 * k:3 * k + 3]
+        return dxn, dvn
+
+    # ------------------------------------------------------------------ VJP
+    def vjp(self, xb, vb):
+        """Cotangents of (x+, v+) (3n,) -> cotangents of (x, v, u)."""
+        inst, lay = self.inst, self.lay
+        dt, gam = inst.dt, inst.gamma
+        fi, gi = lay.fidx, lay.gidx
+        xb = np.asarray(xb, dtype=np.float64)
+        vb = np.asarray(vb, dtype=np.float64)
+        xbar = np.zeros(3 * self.n)
+        vbar = np.zeros(3 * self.n)
+        ubar = np.zeros(3 * len(inst.grip_nodes))
+        # v+_f = (x+_f - x_f)/dt ; x+_g = b ; v+_g = u
+        xnb_f = xb[fi] + vb[fi] / dt
+        xbar[fi] -= vb[fi] / dt
+        bbar = np.zeros(3 * self.n)
+        bbar[gi] = xb[gi]
+        for k, j in enumerate(inst.grip_nodes):
+            ubar[3 * k:3 * k + 3] += vb[3 * j:3 * j + 3]
+        # stage 2
+        if self.kappa > 0.0:
+            z = self.Klu.solve(xnb_f)
+            ybar_f = self.J.T @ z
+            bbar[gi] -= self.Wfg.T @ z
+        else:
+            nf = len(fi)
+            rhs = np.concatenate([xnb_f, np.zeros(self.nA)])
+            sol = np.linalg.solve(self.Kkkt.T, rhs)
+            a, c = sol[:nf], sol[nf:]
+            ybar_f = xnb_f - (self.Wff - self.C).T @ a
+            if self.nA:
+                ybar_f = ybar_f - (self.NA + self.RA).T @ c
+            bbar[gi] -= self.Wfg.T @ a
+        # stage 1
+        mu = self.Hlu.solve(ybar_f)
+        xhatb_f = inst.mass / dt ** 2 * mu
+        bbar[gi] -= self.Hfg.T @ mu
+        xbar[fi] += xhatb_f
+        vbar[fi] += dt * (1.0 - gam) * xhatb_f
+        for k, j in enumerate(inst.grip_nodes):
+            xbar[3 * j:3 * j + 3] += bbar[3 * j:3 * j + 3]
+            ubar[3 * k:3 * k + 3] += dt * bbar[3 * j:3 * j + 3]
+        return xbar, vbar, ubar
+
+    # ---------------------------------------------------------------- dense
+    def dense(self):
+        """A = ds+/ds (6n x 6n), B = ds+/du (6n x n_u)."""
+        n3 = 3 * self.n
+        nu = 3 * len(self.inst.grip_nodes)
+        I = np.eye(n3)
+        Z = np.zeros((n3, n3))
+        ax, av = self.jvp(I, Z, np.zeros((nu, n3)))
+        bx, bv = self.jvp(Z, I, np.zeros((nu, n3)))
+        cx, cv = self.jvp(np.zeros((n3, nu)), np.zeros((n3, nu)), np.eye(nu))
+        A = np.block([[ax, bx], [av, bv]])
+        B = np.vstack([cx, cv])
+        return A, B
+
+
+def rollout_backward(inst, traj, sT_bar=None, traj_bar=None, kappa=None):
+    """Reverse-mode gradient of a rollout through f_kappa (default kappa_bwd),
+    linearised at the stored states.  Returns (s0_bar (6n,), u_bar (T, n_u))."""
+    kappa = inst.kappa_bwd if kappa is None else kappa
+    n, T = inst.n, inst.T
+    el = model.elements(inst)
+    lay = Layout(inst)
+    sb = np.zeros(6 * n) if sT_bar is None else np.array(sT_bar, dtype=np.float64)
+    if traj_bar is not None:
+        sb = sb + traj_bar[T]
+    ubar = np.zeros((T, 3 * len(inst.grip_nodes)))
+    for t in range(T - 1, -1, -1):
+        d = StepDerivative(inst, traj[t], inst.u[t], kappa, el, lay)
+        xb, vb, ub = d.vjp(sb[:3 * n], sb[3 * n:])
+        sb = np.concatenate([xb, vb])
+        if traj_bar is not None:
+            sb = sb + traj_bar[t]
+        ubar[t] = ub
+    return sb, ubar
+
+
+def rollout_jvp(inst, traj, ds0, du, kappa=None):
+    """Forward-mode tangent of a rollout: ds0 (6n, m), du (T, n_u, m) ->
+    ds (T+1, 6n, m)."""
+    kappa = inst.kappa_bwd if kappa is None else kappa
+    n, T = inst.n, inst.T
+    el = model.elements(inst)
+    lay = Layout(inst)
+    ds0 = np.asarray(ds0, dtype=np.float64)
+    if ds0.ndim == 1:
+        ds0 = ds0[:, None]
+        du = np.asarray(du)[:, :, None]
+    out = np.zeros((T + 1,) + ds0.shape)
+    out[0] = ds0
+    for t in range(T):
+        d = StepDerivative(inst, traj[t], inst.u[t], kappa, el, lay)
+        dxn, dvn = d.jvp(out[t][:3 * n], out[t][3 * n:], du[t])
+        out[t + 1] = np.vstack([dxn, dvn])
+    return out
+
+
+def rollout_linearize(inst, traj, kappa=None):
+    """Dense A_t, B_t along a trajectory: arrays (T, 6n, 6n) and (T, 6n, n_u)."""
+    kappa = inst.kappa_bwd if kappa is None else kappa
+    el = model.elements(inst)
+    lay = Layout(inst)
+    As, Bs = [], []
+    for t in range(inst.T):
+        A, B = StepDerivative(inst, traj[t], inst.u[t], kappa, el, lay).dense()
+        As.append(A)
+        Bs.append(B)
+    return np.array(As), np.array(Bs)
+
+
+__all__ = ["StepDerivative", "rollout_backward", "rollout_jvp", "rollout_linearize", "rollout"]

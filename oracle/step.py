@@ -1,0 +1,326 @@
+"""One simulator step q+ = f(q, u) and rollouts, in FP64 (Sec. 4.1).
+
+The step follows the paper's two-stage solver (paragraph "Simulation
+Solver"), with the readings stated below where the paper is silent.
+
+1. Grippers (eq. holonomic-constraint, grasp taken in its D -> infinity
+   limit): gripper k holds node j; x+_j = x_j + dt u_k, v+_j = u_k, and node j
+   is removed from the unknowns.
+2. Predictor: x_hat = x + dt (1 - gamma) v.  gamma = 1 is exactly the paper's
+   quasi-static eq. (dynamics) with M (q+ - q)/dt^2; gamma < 1 keeps a
+   fraction of the velocity (damped implicit Euler).
+3. Stage 1 (eq. dynamics-first-stage): find y* with
+   F(y) = M (y - x_hat)/dt^2 + dE/dy - M g = 0 over the free nodes.  F is the
+   gradient of Psi(y) = |y - x_hat|_M^2 / (2 dt^2) + E(y) - (M g)^T y, so the
+   Newton iteration is a minimisation: direction from the spring-projected
+   Hessian, Armijo backtracking on Psi, stop at |F|_inf <= 1e-10 (1 + |M g|_inf).
+4. Stage 2 (eq. dynamics-second-stage) at y*: P = dF/dy (y*) (the exact
+   Hessian of Psi, consistent with the stage-1 units), one contact pair per
+   (free node, obstacle), signed distance phi_c and normal n_c at y*.
+   * kappa > 0 (Contact Smoothing paragraph): P D = sum_c n_c lam_c with
+     lam_c gap_c = kappa, gap_c = phi_c + n_c . D_p > 0, lam_c > 0;
+   * kappa = 0: the QP min 1/2 D^T P D s.t. phi_c + n_c . D_p >= 0.
+   Both are solved by a primal-dual interior-point iteration on
+   (D, lam, gap); the hard case then fixes the active set and solves the
+   equality-constrained KKT system exactly.
+5. x+ = y* + D on free nodes, v+ = (x+ - x)/dt.
+
+Friction is zero (the friction cone reduces to the normal half-line).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import (STATUS_NEWTON_NOCONV, STATUS_NONFINITE, STATUS_NOT_PD, STATUS_OK,
+               STATUS_QP_NOCONV, model, sdf)
+
+
+@dataclass
+class StepResult:
+    x: np.ndarray          # (n, 3) next positions
+    v: np.ndarray          # (n, 3) next velocities
+    y: np.ndarray          # (n, 3) stage-1 solution y* (gripped nodes at their targets)
+    delta: np.ndarray      # (n, 3) stage-2 correction (0 on gripped nodes)
+    xhat: np.ndarray       # (n, 3) predictor
+    pair_node: np.ndarray  # (nc,) node of each contact pair
+    pair_obs: np.ndarray   # (nc,) obstacle of each contact pair
+    phi: np.ndarray        # (nc,) signed distance at y*
+    normal: np.ndarray     # (nc, 3) SDF gradient at y*
+    curv: np.ndarray       # (nc, 3, 3) SDF Hessian at y*
+    lam: np.ndarray        # (nc,) contact force magnitudes
+    gap: np.ndarray        # (nc,) phi + n . delta
+    active: np.ndarray     # (nc,) hard mode: pairs held at gap 0
+    kappa: float
+    status: int = STATUS_OK
+    newton_iters: int = 0
+    ipm_iters: int = 0
+    extra: dict = field(default_factory=dict)
+
+
+class Layout:
+    """Free/gripped bookkeeping for one instance."""
+
+    def __init__(self, inst):
+        n = inst.n
+        self.n = n
+        self.grip_of = -np.ones(n, dtype=np.int64)
+        for k, j in enumerate(inst.grip_nodes):
+            self.grip_of[j] = k
+        self.free = self.grip_of < 0
+        self.free_nodes = np.nonzero(self.free)[0]
+        self.grip_nodes = np.array(inst.grip_nodes, dtype=np.int64)
+        dof = np.arange(3 * n).reshape(n, 3)
+        self.fidx = dof[self.free].ravel()
+        self.gidx = dof[~self.free].ravel()
+        self.fpos = -np.ones(n, dtype=np.int64)
+        self.fpos[self.free_nodes] = np.arange(len(self.free_nodes))
+
+
+def mass_diag(inst, lay: Layout) -> np.ndarray:
+    """Diagonal of M/dt^2 on the free DoFs."""
+    return np.full(len(lay.fidx), inst.mass / inst.dt ** 2)
+
+
+def gripper_targets(inst, lay: Layout, x, u_t):
+    """b_j = x_j + dt u_k for every gripped node j held by gripper k."""
+    b = np.zeros((inst.n, 3))
+    u = np.asarray(u_t).reshape(-1, 3)
+    for k, j in enumerate(inst.grip_nodes):
+        b[j] = x[j] + inst.dt * u[k]
+    return b
+
+
+def psi_gradient(inst, el, lay, y, xhat):
+    """F(y) of eq. (dynamics-first-stage) on the free nodes, zero elsewhere."""
+    F = model.gradient(el, y)
+    F = F + inst.mass / inst.dt ** 2 * (y - xhat) - inst.mass * inst.gravity[None, :]
+    F[~lay.free] = 0.0
+    return F
+
+
+def psi_difference(inst, el, lay, y0, y1, xhat):
+    """Psi(y1) - Psi(y0) in cancellation-free form."""
+    dE = model.energy_difference(el, y0, y1)
+    f = lay.free
+    dy = (y1 - y0)[f]
+    dM = inst.mass / (2.0 * inst.dt ** 2) * np.sum(dy * (y1[f] + y0[f] - 2.0 * xhat[f]))
+    dG = -inst.mass * np.sum(dy @ inst.gravity)
+    return dE + dM + dG
+
+
+def psi_hessian_ff(inst, el, lay, y, project):
+    """d^2 Psi / dy^2 restricted to the free DoFs (sparse)."""
+    H = model.hessian(el, y, project=project)
+    Hff = H[lay.fidx][:, lay.fidx] + sp.diags(mass_diag(inst, lay))
+    return Hff.tocsc()
+
+
+def stage1(inst, el, lay, y0, xhat, max_iter=100):
+    """Newton's method on F(y) = 0 (minimising Psi) from y0."""
+    y = y0.copy()
+    scale = 1.0 + inst.mass * float(np.max(np.abs(inst.gravity)))
+    tol = 1e-10 * scale
+    it = 0
+    for it in range(max_iter):
+        F = psi_gradient(inst, el, lay, y, xhat)
+        if not np.all(np.isfinite(F)):
+            return y, STATUS_NONFINITE, it
+        if np.max(np.abs(F), initial=0.0) <= tol:
+            return y, STATUS_OK, it
+        Hp = psi_hessian_ff(inst, el, lay, y, project=True)
+        g = F.ravel()[lay.fidx]
+        d = spla.spsolve(Hp, -g)
+        D = np.zeros(3 * inst.n)
+        D[lay.fidx] = d
+        D = D.reshape(inst.n, 3)
+        gTd = float(g @ d)
+        alpha = 1.0
+        for _ in range(60):
+            if psi_difference(inst, el, lay, y, y + alpha * D, xhat) <= 1e-4 * alpha * gTd:
+                break
+            alpha *= 0.5
+        y = y + alpha * D
+        if np.max(np.abs(alpha * D)) <= 1e-16 * (1.0 + np.max(np.abs(y))):
+            break
+    F = psi_gradient(inst, el, lay, y, xhat)
+    ok = np.max(np.abs(F), initial=0.0) <= 1e3 * tol
+    return y, (STATUS_OK if ok else STATUS_NEWTON_NOCONV), it + 1
+
+
+def contact_pairs(inst, lay, y):
+    """All (free node, obstacle) pairs with phi, n and SDF Hessian at y."""
+    nodes, obs, phis, ns, Hs = [], [], [], [], []
+    pts = y[lay.free_nodes]
+    for o, fn in enumerate(sdf.obstacles(inst)):
+        phi, nrm, H = fn(pts)
+        nodes.append(lay.free_nodes.copy())
+        obs.append(np.full(len(pts), o))
+        phis.append(phi); ns.append(nrm); Hs.append(H)
+    if not nodes:
+        z = np.zeros(0)
+        return (np.zeros(0, dtype=np.int64), np.zeros(0, dtype=np.int64), z,
+                np.zeros((0, 3)), np.zeros((0, 3, 3)))
+    return (np.concatenate(nodes), np.concatenate(obs), np.concatenate(phis),
+            np.concatenate(ns), np.concatenate(Hs))
+
+
+def normal_matrix(lay, pair_node, normal):
+    """N: one row n_c^T per pair, placed at the free DoFs of its node."""
+    nc = len(pair_node)
+    rows = np.repeat(np.arange(nc), 3)
+    cols = (3 * lay.fpos[pair_node][:, None] + np.arange(3)[None]).ravel()
+    return sp.csr_matrix((normal.ravel(), (rows, cols)), shape=(nc, 3 * len(lay.free_nodes)))
+
+
+def interior_point(P, N, phi, kappa, fscale, xscale, max_iter=300):
+    """Primal-dual Newton on  P D - N^T lam = 0,  gap - phi - N D = 0,
+    lam * gap = mu,  with gap, lam > 0 (infeasible start).  For kappa > 0
+    mu = kappa throughout; for kappa = 0 mu is driven to ~0."""
+    nc = len(phi)
+    ndof = P.shape[0]
+    D = np.zeros(ndof)
+    if nc == 0:
+        return D, np.zeros(0), np.zeros(0), 0, True
+    pii = np.asarray((N @ P).multiply(N).sum(axis=1)).ravel()
+    hard = kappa <= 0.0
+    mu = kappa if not hard else max(1e-2 * float(np.mean(pii * phi ** 2)), 1e-12)
+    gap = 0.5 * (phi + np.sqrt(phi ** 2 + 4.0 * mu / pii))
+    lam = mu / gap
+    NT = N.T.tocsr()
+    for it in range(max_iter):
+        rd = P @ D - NT @ lam
+        rp = gap - phi - N @ D
+        rc = lam * gap - mu
+        done_res = (np.max(np.abs(rd)) <= 1e-13 * fscale and np.max(np.abs(rp)) <= 1e-13 * xscale)
+        if not hard:
+            if done_res and np.max(np.abs(rc)) <= 1e-12 * kappa:
+                return D, lam, gap, it, True
+        else:
+            if done_res and np.max(lam * gap) <= 1e-14 * fscale * xscale:
+                return D, lam, gap, it, True
+            mu = max(0.1 * float(np.mean(lam * gap)), 1e-18 * fscale * xscale)
+            rc = lam * gap - mu
+        w = lam / gap
+        Kip = (P + NT @ sp.diags(w) @ N).tocsc()
+        rhs = -rd + NT @ ((-rc + lam * rp) / gap)
+        dD = spla.spsolve(Kip, rhs)
+        dgap = N @ dD - rp
+        dlam = (-rc - lam * dgap) / gap
+        alpha = 1.0
+        neg = dgap < 0
+        if np.any(neg):
+            alpha = min(alpha, 0.995 * float(np.min(-gap[neg] / dgap[neg])))
+        neg = dlam < 0
+        if np.any(neg):
+            alpha = min(alpha, 0.995 * float(np.min(-lam[neg] / dlam[neg])))
+        D = D + alpha * dD
+        gap = gap + alpha * dgap
+        lam = lam + alpha * dlam
+    return D, lam, gap, max_iter, False
+
+
+def hard_crossover(P, N, phi, D, lam, gap, fscale, xscale):
+    """Fix the active set {lam > pi gap} and solve the KKT system
+    [[P, -N_A^T], [N_A, 0]] [D; lam_A] = [0; -phi_A] exactly (dense, least
+    squares so degenerate normals are allowed)."""
+    pii = np.asarray((N @ P).multiply(N).sum(axis=1)).ravel()
+    act = lam > pii * gap
+    Pd = P.toarray()
+    Nd = N.toarray()
+    NA = Nd[act]
+    na = NA.shape[0]
+    ndof = Pd.shape[0]
+    Kk = np.block([[Pd, -NA.T], [NA, np.zeros((na, na))]])
+    rhs = np.concatenate([np.zeros(ndof), -phi[act]])
+    sol = np.linalg.lstsq(Kk, rhs, rcond=None)[0]
+    D2 = sol[:ndof]
+    lamA = sol[ndof:]
+    gap2 = phi + Nd @ D2
+    lam2 = np.zeros_like(lam)
+    lam2[act] = lamA
+    ok = (np.all(gap2 >= -1e-11 * xscale) and np.all(lamA >= -1e-9 * fscale)
+          and np.max(np.abs(Pd @ D2 - Nd.T @ lam2), initial=0.0) <= 1e-9 * fscale)
+    return D2, lam2, gap2, act, ok
+
+
+def step(inst, x, v, u_t, kappa, el=None, lay=None) -> StepResult:
+    """q+ = f(q, u) with contact relaxation kappa (kappa = 0: hard contact)."""
+    el = model.elements(inst) if el is None else el
+    lay = Layout(inst) if lay is None else lay
+    dt, gamma = inst.dt, inst.gamma
+    x = np.asarray(x, dtype=np.float64).reshape(inst.n, 3)
+    v = np.asarray(v, dtype=np.float64).reshape(inst.n, 3)
+    u = np.asarray(u_t, dtype=np.float64).reshape(-1, 3)
+    b = gripper_targets(inst, lay, x, u)
+    xhat = x + dt * (1.0 - gamma) * v
+    y0 = xhat.copy()
+    y0[~lay.free] = b[~lay.free]
+    status = STATUS_OK
+    if not (np.all(np.isfinite(x)) and np.all(np.isfinite(v)) and np.all(np.isfinite(u))):
+        nan = np.full((inst.n, 3), np.nan)
+        e = np.zeros(0)
+        return StepResult(nan, nan, nan, nan, xhat, e.astype(int), e.astype(int), e,
+                          np.zeros((0, 3)), np.zeros((0, 3, 3)), e, e, e.astype(bool),
+                          kappa, STATUS_NONFINITE)
+    y, st1, it1 = stage1(inst, el, lay, y0, xhat)
+    status = max(status, st1)
+
+    pn, po, phi, nrm, curv = contact_pairs(inst, lay, y)
+    P = psi_hessian_ff(inst, el, lay, y, project=False)
+    fscale = inst.mass / dt ** 2 * inst.h + inst.mass * float(np.max(np.abs(inst.gravity)))
+    xscale = inst.h
+    delta = np.zeros((inst.n, 3))
+    lam = np.zeros(len(phi))
+    gap = phi.copy()
+    active = np.zeros(len(phi), dtype=bool)
+    it2 = 0
+    if len(phi):
+        try:
+            np.linalg.cholesky(P.toarray()) if P.shape[0] <= 1200 else None
+        except np.linalg.LinAlgError:
+            status = max(status, STATUS_NOT_PD)
+        N = normal_matrix(lay, pn, nrm)
+        D, lam, gap, it2, ok = interior_point(P, N, phi, kappa, fscale, xscale)
+        if kappa <= 0.0:
+            D, lam, gap, active, ok2 = hard_crossover(P, N, phi, D, lam, gap, fscale, xscale)
+            ok = ok and ok2
+        if not ok:
+            status = max(status, STATUS_QP_NOCONV)
+        full = np.zeros(3 * inst.n)
+        full[lay.fidx] = D
+        delta = full.reshape(inst.n, 3)
+
+    xn = y + delta
+    xn[~lay.free] = b[~lay.free]
+    vn = (xn - x) / dt
+    for k, j in enumerate(inst.grip_nodes):
+        vn[j] = u[k]
+    if not (np.all(np.isfinite(xn)) and np.all(np.isfinite(vn))):
+        status = STATUS_NONFINITE
+    return StepResult(xn, vn, y, delta, xhat, pn, po, phi, nrm, curv, lam, gap, active,
+                      kappa, status, it1, it2)
+
+
+def rollout(inst, kappa=None, s0=None, u=None):
+    """Roll out inst.T steps.  Returns (traj (T+1, 6n), status per step)."""
+    kappa = inst.kappa_fwd if kappa is None else kappa
+    s0 = inst.s0 if s0 is None else s0
+    u = inst.u if u is None else u
+    el = model.elements(inst)
+    lay = Layout(inst)
+    n = inst.n
+    traj = np.zeros((inst.T + 1, 6 * n))
+    traj[0] = s0
+    stat = np.zeros(inst.T, dtype=np.int64)
+    for t in range(inst.T):
+        x = traj[t, :3 * n].reshape(n, 3)
+        v = traj[t, 3 * n:].reshape(n, 3)
+        r = step(inst, x, v, u[t], kappa, el, lay)
+        traj[t + 1, :3 * n] = r.x.ravel()
+        traj[t + 1, 3 * n:] = r.v.ravel()
+        stat[t] = r.status
+    return traj, stat

@@ -1,0 +1,256 @@
+"""Seeded synthetic rope and cloth instances.
+
+Shapes follow the paper's objects: a rope of about 0.8 m (perception appendix,
+rope subsection) and a cloth of about 38 cm square (cloth subsection).  The
+paper names no benchmark suite for its simulator, so every instance here is
+synthetic; the recipes are the configurations the simulator is benchmarked on:
+
+* ``config_c1``: one 20-node rope, 50 steps, ground + one sphere.
+* ``config_c2``: 1024 ropes of 64 nodes, 100 steps, ground + 3 random spheres.
+* ``config_c3``: 256 cloths of 32x32 nodes, 60 steps, ground + sphere + box.
+* ``config_c4``: 4096 mixed ropes (16..256 nodes) and cloths (8x8..48x48).
+
+Random numbers come from ``numpy.random.Generator(PCG64)``; a batch uses one
+child stream per instance from ``SeedSequence(seed).spawn(B)`` so that an
+instance's inputs do not depend on the batch it is drawn in.
+
+State layout of one instance (``n`` nodes): ``s = [x_0 .. x_{n-1} | v_0 .. v_{n-1}]``
+with xyz interleaved, i.e. ``6n`` floats.  Controls are gripper velocities,
+``u[t] = [u_0 | u_1 | ...]`` (3 per gripper).  A cloth node ``(ix, iy)`` has
+index ``iy * nx + ix``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+ROPE = "rope"
+CLOTH = "cloth"
+
+
+@dataclasses.dataclass
+class Instance:
+    kind: str                 # "rope" | "cloth"
+    nx: int                   # rope: number of nodes; cloth: nodes along x
+    ny: int                   # rope: 1; cloth: nodes along y
+    h: float                  # rest spacing between grid neighbours [m]
+    mass: float               # lumped mass per node [kg]
+    k_struct: float           # stretch / structural spring stiffness [N/m]
+    k_shear: float            # cloth shear spring stiffness [N/m] (rope: unused)
+    k_bend: float             # rope: discrete-curvature stiffness; cloth: bend spring [N/m]
+    grip_nodes: tuple         # node held by gripper k (Dirichlet grasp)
+    ground: bool              # plane z = 0
+    spheres: np.ndarray       # (ns, 4): cx, cy, cz, r
+    boxes: np.ndarray         # (nb, 7): cx, cy, cz, hx, hy, hz, rounding
+    dt: float
+    gamma: float              # velocity damping: predictor x + dt (1 - gamma) v
+    gravity: np.ndarray       # (3,)
+    kappa_fwd: float          # contact relaxation used by forward rollouts [J]
+    kappa_bwd: float          # contact relaxation used for derivatives [J]
+    T: int                    # horizon
+    s0: np.ndarray            # (6n,) initial state
+    u: np.ndarray             # (T, 3 * n_grip) controls
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny
+
+    @property
+    def n_s(self) -> int:
+        return 6 * self.n
+
+    @property
+    def n_u(self) -> int:
+        return 3 * len(self.grip_nodes)
+
+    def replace(self, **kw) -> "Instance":
+        return dataclasses.replace(self, **kw)
+
+
+def contact_kappa(mass: float, dt: float, width: float) -> float:
+    """Contact relaxation for a smoothing width: kappa = (m / dt^2) * width^2.
+
+    With this choice an isolated particle resting on a surface (signed
+    distance 0) settles at a gap equal to ``width``.
+    """
+    return mass / dt ** 2 * width ** 2
+
+
+def _grid_positions(nx: int, ny: int, h: float, z0: float) -> np.ndarray:
+    ix, iy = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    pos = np.stack([ix.ravel() * h, iy.ravel() * h, np.full(nx * ny, z0)], axis=1)
+    return pos.astype(np.float64)
+
+
+def rope(n: int, *, length: float = 0.8, z0: float = 0.1, k: float = 500.0,
+         k_bend: float = 5.0, mass: float = 0.01, dt: float = 0.005,
+         gamma: float = 0.02, T: int = 50, grip_nodes=(0,), ground: bool = True,
+         spheres=(), boxes=(), width: float = 1e-3, kappa_fwd=None,
+         kappa_bwd=None, u=None, gravity=(0.0, 0.0, -9.81), h=None,
+         s0=None) -> Instance:
+    """A straight rope along +x at height ``z0``, at rest."""
+    h = (length / (n - 1) if n > 1 else length) if h is None else h
+    kap = contact_kappa(mass, dt, width)
+    pos = _grid_positions(n, 1, h, z0)
+    if s0 is None:
+        s0 = np.concatenate([pos.ravel(), np.zeros(3 * n)])
+    n_u = 3 * len(grip_nodes)
+    if u is None:
+        u = np.zeros((T, n_u))
+    return Instance(
+        kind=ROPE, nx=n, ny=1, h=float(h), mass=float(mass), k_struct=float(k),
+        k_shear=0.0, k_bend=float(k_bend), grip_nodes=tuple(int(g) for g in grip_nodes),
+        ground=bool(ground), spheres=np.asarray(spheres, dtype=np.float64).reshape(-1, 4),
+        boxes=np.asarray(boxes, dtype=np.float64).reshape(-1, 7), dt=float(dt),
+        gamma=float(gamma), gravity=np.asarray(gravity, dtype=np.float64),
+        kappa_fwd=float(kap if kappa_fwd is None else kappa_fwd),
+        kappa_bwd=float(kap if kappa_bwd is None else kappa_bwd), T=int(T),
+        s0=np.asarray(s0, dtype=np.float64), u=np.asarray(u, dtype=np.float64))
+
+
+def cloth(nx: int, ny: int, *, size: float = 0.38, z0: float = 0.1,
+          k_struct: float = 500.0, k_shear: float = 250.0, k_bend: float = 5.0,
+          mass: float = 0.01, dt: float = 0.002, gamma: float = 0.02, T: int = 60,
+          grip_nodes=None, ground: bool = True, spheres=(), boxes=(),
+          width: float = 1e-3, kappa_fwd=None, kappa_bwd=None, u=None,
+          gravity=(0.0, 0.0, -9.81), s0=None) -> Instance:
+    """A flat square-cell cloth in the plane z = ``z0``, at rest.
+
+    By default the two corners of the ``iy = 0`` edge are gripped.
+    """
+    h = size / (max(nx, ny) - 1)
+    if grip_nodes is None:
+        grip_nodes = (0, nx - 1)
+    kap = contact_kappa(mass, dt, width)
+    pos = _grid_positions(nx, ny, h, z0)
+    if s0 is None:
+        s0 = np.concatenate([pos.ravel(), np.zeros(3 * nx * ny)])
+    n_u = 3 * len(grip_nodes)
+    if u is None:
+        u = np.zeros((T, n_u))
+    return Instance(
+        kind=CLOTH, nx=nx, ny=ny, h=float(h), mass=float(mass), k_struct=float(k_struct),
+        k_shear=float(k_shear), k_bend=float(k_bend),
+        grip_nodes=tuple(int(g) for g in grip_nodes), ground=bool(ground),
+        spheres=np.asarray(spheres, dtype=np.float64).reshape(-1, 4),
+        boxes=np.asarray(boxes, dtype=np.float64).reshape(-1, 7), dt=float(dt),
+        gamma=float(gamma), gravity=np.asarray(gravity, dtype=np.float64),
+        kappa_fwd=float(kap if kappa_fwd is None else kappa_fwd),
+        kappa_bwd=float(kap if kappa_bwd is None else kappa_bwd), T=int(T),
+        s0=np.asarray(s0, dtype=np.float64), u=np.asarray(u, dtype=np.float64))
+
+
+# --------------------------------------------------------------------------
+# random obstacle recipes
+# --------------------------------------------------------------------------
+
+def _rope_spheres(rng: np.random.Generator, length: float, z0: float, count: int = 3,
+                  clearance: float = 0.005) -> np.ndarray:
+    """Spheres r ~ U[0.03, 0.08], centre x ~ U[0.1, 0.7] (scaled to the rope
+    length), y ~ U[-0.1, 0.1], z ~ U[0, r]; a draw closer than r + 5 mm to
+    the initial rope is rejected and redrawn."""
+    out = []
+    scale = length / 0.8
+    while len(out) < count:
+        r = rng.uniform(0.03, 0.08)
+        c = np.array([rng.uniform(0.1, 0.7) * scale, rng.uniform(-0.1, 0.1),
+                      rng.uniform(0.0, r)])
+        xc = min(max(c[0], 0.0), length)
+        dist = math.sqrt((c[0] - xc) ** 2 + c[1] ** 2 + (c[2] - z0) ** 2)
+        if dist > r + clearance:
+            out.append([c[0], c[1], c[2], r])
+    return np.array(out, dtype=np.float64)
+
+
+def _cloth_obstacles(rng: np.random.Generator, size: float, z0: float):
+    """One sphere under the cloth interior (top at least 1 cm below the
+    cloth) and one rounded box resting on the ground (top at least 1 cm
+    below the cloth)."""
+    r = rng.uniform(0.03, 0.08)
+    cz = rng.uniform(0.0, max(0.0, min(r, z0 - 0.01 - r)))
+    sph = np.array([[rng.uniform(0.25, 0.75) * size, rng.uniform(0.25, 0.75) * size, cz, r]])
+    hx, hy = rng.uniform(0.02, 0.05, size=2)
+    hz = rng.uniform(0.02, min(0.05, (z0 - 0.01) / 2.0))
+    box = np.array([[rng.uniform(0.2, 0.8) * size, rng.uniform(0.2, 0.8) * size, hz,
+                     hx, hy, hz, 0.005]])
+    return sph, box
+
+
+def _streams(seed: int, count: int):
+    return [np.random.Generator(np.random.PCG64(s)) for s in np.random.SeedSequence(seed).spawn(count)]
+
+
+# --------------------------------------------------------------------------
+# benchmark configurations
+# --------------------------------------------------------------------------
+
+C1_GOAL = np.array([0.7, 0.2, 0.0])
+
+
+def config_c1(seed: int = 1001) -> Instance:
+    """Single 20-node rope, 50 steps; node 0 gripped; ground + sphere at
+    (0.4, 0, 0.05), r = 0.05; controls ~ N(0, 0.05^2)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T = 50
+    u = rng.normal(0.0, 0.05, size=(T, 3))
+    return rope(20, k=500.0, k_bend=5.0, mass=0.01, dt=0.005, gamma=0.02, T=T,
+                spheres=[[0.4, 0.0, 0.05, 0.05]], u=u)
+
+
+def _c2_instance(rng, n=64, T=100) -> Instance:
+    k = rng.uniform(300.0, 800.0)
+    sph = _rope_spheres(rng, 0.8, 0.1)
+    u = rng.normal(0.0, 0.05, size=(T, 3))
+    return rope(n, k=k, k_bend=5.0, mass=0.01, dt=0.005, gamma=0.02, T=T,
+                spheres=sph, u=u)
+
+
+def config_c2(B: int = 1024, seed: int = 1002, n: int = 64, T: int = 100):
+    """Ropes of 64 nodes, 100 steps, k ~ U[300, 800], 3 random spheres."""
+    return [_c2_instance(rng, n, T) for rng in _streams(seed, B)]
+
+
+def _c3_instance(rng, nx=32, ny=32, T=60) -> Instance:
+    sph, box = _cloth_obstacles(rng, 0.38, 0.1)
+    u = rng.normal(0.0, 0.02, size=(T, 6))
+    return cloth(nx, ny, k_struct=500.0, k_shear=250.0, k_bend=5.0, mass=0.01,
+                 dt=0.002, gamma=0.02, T=T, spheres=sph, boxes=box, u=u)
+
+
+def config_c3(B: int = 256, seed: int = 1003, nx: int = 32, ny: int = 32, T: int = 60):
+    """Cloths of 32x32 nodes, 60 steps, ground + sphere + box, corners gripped."""
+    return [_c3_instance(rng, nx, ny, T) for rng in _streams(seed, B)]
+
+
+def config_c4(B: int = 4096, seed: int = 1004):
+    """Mixed batch: rope (n log-uniform on [16, 256]) or cloth (side
+    log-uniform on [8, 48]) with probability 1/2; T ~ U{30..120}."""
+    out = []
+    for rng in _streams(seed, B):
+        T = int(rng.integers(30, 121))
+        if rng.random() < 0.5:
+            n = int(round(math.exp(rng.uniform(math.log(16), math.log(256)))))
+            out.append(_c2_instance(rng, n, T))
+        else:
+            side = int(round(math.exp(rng.uniform(math.log(8), math.log(48)))))
+            out.append(_c3_instance(rng, side, side, T))
+    return out
+
+
+def small_rope_batch(B: int, n: int, T: int, seed: int):
+    """C2-style ropes at a smaller size (parity tests)."""
+    return [_c2_instance(rng, n, T) for rng in _streams(seed, B)]
+
+
+def small_cloth_batch(B: int, nx: int, ny: int, T: int, seed: int):
+    """C3-style cloths at a smaller size (parity tests)."""
+    return [_c3_instance(rng, nx, ny, T) for rng in _streams(seed, B)]
+
+
+def random_cotangent(size: int, seed: int) -> np.ndarray:
+    """A seeded unit vector used as the terminal-state cotangent."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = rng.normal(size=size)
+    return w / np.linalg.norm(w)
