@@ -1,0 +1,277 @@
+/*
+ * cord.h - C ABI of libcord: batched, differentiable rope and cloth
+ * simulation with smoothed contact on AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow the simulator of "Robustness without Wrinkles:
+ * Parallel Simulation and Robust MPC for Certified Deformable Manipulation"
+ * (CORD-SLS):
+ *   - Sec. 3, Problem 1 / eq. (dynamics_sim): the planner dynamics
+ *     q_{k+1} = f(q_k, u_k) with configuration q and control u;
+ *   - Sec. 4.1, eqs. (dynamics), (holonomic-constraint), (contact-constraint),
+ *     (dynamics-first-stage), (dynamics-second-stage): the two-stage step;
+ *   - Sec. 4.1 "Contact Smoothing": complementarity relaxed to gap*lam = kappa;
+ *   - Sec. 4.1 "Differentiating Through Simulation", eq. (diff-sim): the
+ *     implicit-function backward pass;
+ *   - Sec. 4.2 (output-feedback SLS program): the linearizations A(z,v),
+ *     B(z,v) along a nominal trajectory.
+ *
+ * Conventions shared by every call
+ *   - Every call returns an int: CORD_OK (0) or one of the CORD_E* codes.
+ *     Nothing throws, aborts or exits across this ABI.  cord_last_error()
+ *     returns a thread-local, NUL-terminated message for the last failure
+ *     on the calling thread (valid until the next call on that thread).
+ *   - Buffers named s0, u, traj, A, Bm, ... are DEVICE pointers owned by the
+ *     caller (e.g. torch.Tensor.data_ptr() of a cuda tensor), FP32, never
+ *     aliased with each other.  Descriptors passed by pointer are HOST
+ *     memory and are copied before the call returns.
+ *   - Work is enqueued on the caller's HIP stream (`stream`, a hipStream_t;
+ *     NULL = the default stream) without any hidden synchronisation; the
+ *     call returns once the work is enqueued.  A cord_sim may be used from
+ *     one stream at a time.
+ *   - Device-side solver outcomes are written per instance into
+ *     `inst_status` (device int32[n_inst], may be NULL); read them after
+ *     synchronising the stream.  A non-OK status never stops other
+ *     instances.
+ *
+ * State layout of one instance with n nodes and n_grip grippers
+ *   s = [x_0 .. x_{n-1} | v_0 .. v_{n-1}]   (xyz interleaved), n_s = 6 n
+ *   u = [u_0 | .. | u_{n_grip-1}]           (gripper velocities), n_u = 3 n_grip
+ * Grippers hold their node rigidly (the D -> infinity limit of the
+ * holonomic penalty of eq. (dynamics-first-stage)): x+_j = x_j + dt u_k,
+ * v+_j = u_k.
+ *
+ * Batches may be ragged (different n, T per instance).  Every I/O buffer is
+ * the concatenation of per-instance blocks in instance order; the block
+ * sizes are given with each call below and cord_sim_offsets() returns the
+ * float offset of every block.  For a uniform batch the layout is simply
+ * [B][...].
+ */
+#ifndef CORD_H
+#define CORD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+#define CORD_OK            0
+#define CORD_EINVAL        1   /* invalid argument or descriptor            */
+#define CORD_ENOMEM        2   /* device or host allocation failed          */
+#define CORD_EHIP          3   /* a HIP runtime call failed (see message)   */
+#define CORD_EUNSUPPORTED  4   /* valid but not supported (e.g. mu != 0)    */
+#define CORD_EAGAIN        5   /* queue full, try again                     */
+#define CORD_ETOOBIG       6   /* request larger than the memory budget     */
+
+/* per-instance device status (inst_status[]) */
+#define CORD_ST_OK             0
+#define CORD_ST_NEWTON_NOCONV  1   /* stage-1 Newton hit its iteration cap       */
+#define CORD_ST_NOT_PD         2   /* a solve met non-positive curvature         */
+#define CORD_ST_QP_NOCONV      3   /* stage-2 interior point hit its cap         */
+#define CORD_ST_NONFINITE      4   /* NaN/Inf in inputs or iterates              */
+
+#define CORD_MAX_GRIP    4
+#define CORD_MAX_SPHERE  4
+#define CORD_MAX_BOX     2
+#define CORD_MAX_OBST    4   /* ground + spheres + boxes, per instance          */
+
+#define CORD_ROPE   0
+#define CORD_CLOTH  1
+
+/*
+ * Physical parameters of one instance.
+ *   dt        time step [s], > 0
+ *   gamma     velocity damping in [0, 1]: the stage-1 inertial term is
+ *             M (q* - x_hat)/dt^2 with x_hat = x + dt (1 - gamma) v.
+ *             gamma = 1 is the paper's quasi-static eq. (dynamics).
+ *   gravity   [m/s^2], part of tau(u) in eq. (dynamics)
+ *   kappa_fwd contact relaxation of rollouts [J]; 0 = hard contact
+ *             (eq. contact-constraint with mu = 0)
+ *   kappa_bwd contact relaxation of the derivatives [J], > 0.  kappa_fwd = 0
+ *             < kappa_bwd is the paper's surrogate-gradient mode.
+ *   mu        friction coefficient of the cone F_mu; must be 0
+ *             (otherwise CORD_EUNSUPPORTED).
+ */
+typedef struct {
+    float dt;
+    float gamma;
+    float gravity[3];
+    float kappa_fwd;
+    float kappa_bwd;
+    float mu;
+} cord_params;
+
+/*
+ * One rope or cloth instance (Sec. 4.1: a nodal system with stretching and
+ * bending energy).
+ *   kind      CORD_ROPE: nx nodes in a chain (ny must be 1), stretch springs
+ *             between neighbours (stiffness k_struct, rest h) and a
+ *             discrete-curvature bending term 1/2 k_bend |x_a - 2x_b + x_c|^2.
+ *             CORD_CLOTH: nx*ny grid, node (ix, iy) has index iy*nx + ix;
+ *             structural (k_struct, rest h), shear (k_shear, rest h*sqrt 2)
+ *             and bend springs two nodes apart (k_bend, rest 2h).
+ *   T         horizon (number of steps), >= 1
+ *   mass      lumped mass of every node [kg], > 0
+ *   grip_node node held by gripper k, distinct, in [0, n)
+ *   ground    nonzero: the plane z = 0 is an obstacle
+ *   sphere    (cx, cy, cz, r) with r > 0
+ *   box       (cx, cy, cz, hx, hy, hz, rho): axis-aligned box of half
+ *             extents h with edges rounded by rho, 0 <= rho < min(h)
+ */
+typedef struct {
+    int32_t kind;
+    int32_t nx, ny;
+    int32_t T;
+    float h;
+    float mass;
+    float k_struct, k_shear, k_bend;
+    int32_t n_grip;
+    int32_t grip_node[CORD_MAX_GRIP];
+    int32_t ground;
+    int32_t n_sphere;
+    float sphere[CORD_MAX_SPHERE][4];
+    int32_t n_box;
+    float box[CORD_MAX_BOX][7];
+    cord_params params;
+} cord_instance_desc;
+
+typedef struct cord_sim cord_sim;
+
+/*
+ * Create a simulator for n_inst instances (Sec. 4.1).  The descriptors are
+ * validated and copied; static per-instance data is uploaded to the
+ * current HIP device.
+ * Errors: CORD_EINVAL (n_inst < 1, dt <= 0, gamma outside [0,1], rope with
+ * ny != 1, cloth with nx or ny < 2, n < 1, bad grip/obstacle data, T < 1,
+ * kappa_bwd <= 0 or kappa_fwd < 0, mass <= 0, h <= 0, negative stiffness),
+ * CORD_EUNSUPPORTED (mu != 0, more than CORD_MAX_OBST obstacles, a node
+ * count no kernel configuration covers: ropes up to 256 nodes, cloths up
+ * to 1024 nodes), CORD_ENOMEM, CORD_EHIP.  *out is set only on success.
+ */
+int cord_sim_create(const cord_instance_desc* inst, int32_t n_inst, cord_sim** out);
+
+/* Free a simulator and its device memory (NULL is a no-op).  The caller
+ * must have synchronised every stream that still uses it. */
+int cord_sim_destroy(cord_sim* sim);
+
+/* Sizes, in floats, of the whole-batch buffers. */
+typedef struct {
+    int64_t n_inst;
+    int64_t s_floats;      /* sum n_s           : s0, s0_bar, final states */
+    int64_t u_floats;      /* sum T n_u         : u, u_bar                 */
+    int64_t traj_floats;   /* sum (T+1) n_s     : full trajectory          */
+    int64_t A_floats;      /* sum T n_s^2       : dense A_t                */
+    int64_t B_floats;      /* sum T n_s n_u     : dense B_t                */
+    int32_t max_n;         /* largest node count                          */
+    int32_t max_T;         /* longest horizon                             */
+} cord_sim_info_t;
+
+int cord_sim_info(const cord_sim* sim, cord_sim_info_t* out);
+
+/*
+ * Float offsets of every instance's block (host arrays of n_inst + 1
+ * entries; any pointer may be NULL).  ckpt_every selects the checkpoint
+ * layout of ckpt_off (see cord_rollout_opts); pass 0 if unused.
+ */
+int cord_sim_offsets(const cord_sim* sim, int32_t ckpt_every, int64_t* s_off,
+                     int64_t* u_off, int64_t* traj_off, int64_t* ckpt_off,
+                     int64_t* A_off, int64_t* B_off);
+
+/* ---------------------------------------------------------------- rollout */
+#define CORD_STORE_FULL   0   /* traj holds s_0 .. s_T: (T+1) n_s per instance          */
+#define CORD_STORE_CKPT   1   /* traj holds s_0, s_K, s_2K, .. and s_T:                  */
+                              /*   (ceil(T/K) + 1) n_s per instance                        */
+#define CORD_STORE_FINAL  2   /* traj holds s_T only: n_s per instance                     */
+
+typedef struct {
+    int32_t store;        /* CORD_STORE_*                                         */
+    int32_t ckpt_every;   /* K >= 1 for CORD_STORE_CKPT                          */
+    int32_t use_kappa_bwd;/* nonzero: roll out f with kappa_bwd instead of kappa_fwd */
+    int32_t reserved;
+    uint32_t* counters;   /* optional device uint32[n_inst][4], added to: Newton
+                             iterations, conjugate-gradient iterations (all solves),
+                             interior-point iterations, solved steps                */
+    float* final_state;   /* optional device [n_s] per instance: s_T, in any store mode */
+} cord_rollout_opts;
+
+/*
+ * Forward rollout s_{t+1} = f(s_t, u_t), t < T (eq. dynamics_sim), with the
+ * two-stage step of Sec. 4.1 at kappa_fwd.
+ *   s0   [n_s] per instance            u  [T][n_u] per instance
+ *   traj written per opts->store (see CORD_STORE_*)
+ * opts may be NULL (= FULL storage).  Errors: CORD_EINVAL (NULL buffer,
+ * bad opts), CORD_EHIP (launch failure).
+ */
+int cord_rollout(cord_sim* sim, const float* s0, const float* u, float* traj,
+                 int32_t* inst_status, const cord_rollout_opts* opts, void* stream);
+
+typedef struct {
+    int32_t store;        /* how `traj` was written: CORD_STORE_FULL or _CKPT   */
+    int32_t ckpt_every;   /* K used by the forward pass                        */
+    int32_t use_kappa_bwd;/* the forward pass ran with kappa_bwd (recompute uses it) */
+    int32_t reserved;
+    const float* sT_bar;  /* device [n_s] per instance, used when traj_bar is NULL */
+    uint32_t* counters;   /* optional device uint32[n_inst][4] as in cord_rollout */
+} cord_backward_opts;
+
+/*
+ * Reverse-mode gradient of a rollout (eq. diff-sim): for every step, in
+ * reverse order, the step is re-solved at kappa_bwd from the stored or
+ * recomputed state s_t, then the adjoint solves with the stage-2 KKT
+ * matrix and with dF/dq* are applied.
+ *   u         [T][n_u] per instance (the controls of the forward pass)
+ *   traj      written by cord_rollout with opts->store (FULL or CKPT)
+ *   traj_bar  [T+1][n_s] per instance, cotangent of every state, or NULL
+ *             (then opts->sT_bar is the cotangent of s_T)
+ *   s0_bar    [n_s] per instance (output)
+ *   u_bar     [T][n_u] per instance (output)
+ * With CKPT storage the states inside each segment are recomputed from its
+ * checkpoint with the same kernel configuration as the forward pass, so
+ * they are bitwise equal to a FULL rollout.  The library keeps a device
+ * workspace for the recomputed segment (grown on demand: CORD_ENOMEM if
+ * that fails).
+ */
+int cord_rollout_backward(cord_sim* sim, const float* u, const float* traj,
+                          const float* traj_bar, float* s0_bar, float* u_bar,
+                          int32_t* inst_status, const cord_backward_opts* opts, void* stream);
+
+/* Tangents for cord_linearize's JVP mode: per step t, k tangent pairs
+ * (ds_t, du_t) map to ds_{t+1} = A_t ds_t + B_t du_t (steps independent). */
+typedef struct {
+    int32_t k;            /* tangents per step, >= 1                          */
+    const float* ds;      /* device [T][k][n_s] per instance, or NULL (= 0)   */
+    const float* du;      /* device [T][k][n_u] per instance, or NULL (= 0)   */
+    float* out;           /* device [T][k][n_s] per instance                  */
+} cord_jvp;
+
+/*
+ * Linearizations along a trajectory (Sec. 4.2, A(z,v), B(z,v)): for every
+ * t < T, A_t = ds_{t+1}/ds_t and B_t = ds_{t+1}/du_t of f at kappa_bwd,
+ * evaluated at the stored states traj (FULL storage) and controls u.
+ *   A   [T][n_s][n_s] row-major per instance, or NULL
+ *   Bm  [T][n_s][n_u] row-major per instance, or NULL
+ *   jvp JVP mode (may be NULL); may be combined with A/Bm.
+ * Errors: CORD_EINVAL if A, Bm and jvp are all NULL.
+ */
+int cord_linearize(cord_sim* sim, const float* traj, const float* u, float* A, float* Bm,
+                   const cord_jvp* jvp, int32_t* inst_status, void* stream);
+
+/*
+ * Sizes in bytes of the public structs, for bindings that mirror them:
+ * out[0] cord_params, out[1] cord_instance_desc, out[2] cord_sim_info_t,
+ * out[3] cord_rollout_opts, out[4] cord_backward_opts, out[5] cord_jvp.
+ * Writes min(n, 6) entries of the host array out; returns CORD_EINVAL if
+ * out is NULL.
+ */
+int cord_abi_sizes(int64_t* out, int32_t n);
+
+/* Thread-local message of the last error on this thread ("" if none). */
+const char* cord_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CORD_H */

@@ -1,0 +1,177 @@
+"""Thin Python front end of libcord: builds descriptors, allocates device
+tensors with torch, and calls the C ABI on torch's current stream.
+
+Every operation runs in libcord's HIP kernels; torch only provides device
+memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, byref, c_int64, c_uint32, c_void_p
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr()) if t is not None else c_void_p(0)
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_desc(inst) -> L.InstanceDesc:
+    """Fill a cord_instance_desc from an object with the attributes of
+    workloads.Instance (kind, nx, ny, h, mass, k_*, grip_nodes, ground,
+    spheres, boxes, dt, gamma, gravity, kappa_fwd, kappa_bwd, T)."""
+    d = L.InstanceDesc()
+    d.kind = L.ROPE if inst.kind == "rope" else L.CLOTH
+    d.nx, d.ny, d.T = int(inst.nx), int(inst.ny), int(inst.T)
+    d.h, d.mass = float(inst.h), float(inst.mass)
+    d.k_struct, d.k_shear, d.k_bend = float(inst.k_struct), float(inst.k_shear), float(inst.k_bend)
+    grips = list(inst.grip_nodes)
+    if len(grips) > L.MAX_GRIP:
+        raise ValueError("too many grippers")
+    d.n_grip = len(grips)
+    for i, g in enumerate(grips):
+        d.grip_node[i] = int(g)
+    d.ground = 1 if inst.ground else 0
+    sph = np.asarray(inst.spheres, dtype=np.float64).reshape(-1, 4)
+    box = np.asarray(inst.boxes, dtype=np.float64).reshape(-1, 7)
+    if len(sph) > L.MAX_SPHERE or len(box) > L.MAX_BOX:
+        raise ValueError("too many obstacles")
+    d.n_sphere, d.n_box = len(sph), len(box)
+    for i, s in enumerate(sph):
+        for c in range(4):
+            d.sphere[i][c] = float(s[c])
+    for i, b in enumerate(box):
+        for c in range(7):
+            d.box[i][c] = float(b[c])
+    p = d.params
+    p.dt, p.gamma = float(inst.dt), float(inst.gamma)
+    for c in range(3):
+        p.gravity[c] = float(inst.gravity[c])
+    p.kappa_fwd, p.kappa_bwd, p.mu = float(inst.kappa_fwd), float(inst.kappa_bwd), 0.0
+    return d
+
+
+class Sim:
+    """A batch of (possibly ragged) rope/cloth instances on the current device."""
+
+    def __init__(self, instances, device=None):
+        self.lib = L.load()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.instances = list(instances)
+        B = len(self.instances)
+        arr = (L.InstanceDesc * B)(*[make_desc(i) for i in self.instances])
+        self._h = c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.cord_sim_create(arr, B, byref(self._h)))
+        info = L.SimInfo()
+        L.check(self.lib.cord_sim_info(self._h, byref(info)))
+        self.info = info
+        self.B = B
+        self.n = [i.n for i in self.instances]
+        self.T = [i.T for i in self.instances]
+        self.n_s = [6 * i.n for i in self.instances]
+        self.n_u = [3 * len(i.grip_nodes) for i in self.instances]
+        self._off_cache = {}
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and self._h.value:
+                self.lib.cord_sim_destroy(self._h)
+                self._h = c_void_p()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ layout
+    def offsets(self, ckpt_every: int = 0):
+        """dict of int64 numpy arrays (B + 1 entries): s, u, traj, ckpt, A, B."""
+        key = ckpt_every
+        if key in self._off_cache:
+            return self._off_cache[key]
+        arrs = [(c_int64 * (self.B + 1))() for _ in range(6)]
+        L.check(self.lib.cord_sim_offsets(self._h, ckpt_every, *[ctypes.cast(a, POINTER(c_int64)) if (i != 3 or ckpt_every > 0) else None
+                                                                  for i, a in enumerate(arrs)]))
+        out = {k: np.frombuffer(a, dtype=np.int64).copy() for k, a in zip(["s", "u", "traj", "ckpt", "A", "B"], arrs)}
+        self._off_cache[key] = out
+        return out
+
+    def uniform(self):
+        return len(set(self.n)) == 1 and len(set(self.T)) == 1 and len(set(self.n_u)) == 1
+
+    def _empty(self, floats):
+        return torch.empty(int(floats), dtype=torch.float32, device=self.device)
+
+    def ckpt_floats(self, K):
+        return int(self.offsets(K)["ckpt"][-1])
+
+    # ------------------------------------------------------------ calls
+    def rollout(self, s0, u, store: int = L.STORE_FULL, ckpt_every: int = 10, out=None,
+                status=None, counters=None, use_kappa_bwd=False, final_state=None):
+        """s0: flat float32 cuda tensor (sum n_s), u: flat (sum T n_u).
+        Returns the trajectory buffer (flat) in the requested storage."""
+        if store == L.STORE_FULL:
+            floats = self.info.traj_floats
+        elif store == L.STORE_CKPT:
+            floats = self.ckpt_floats(ckpt_every)
+        else:
+            floats = self.info.s_floats
+        traj = self._empty(floats) if out is None else out
+        o = L.RolloutOpts()
+        o.store, o.ckpt_every, o.use_kappa_bwd = store, ckpt_every, int(bool(use_kappa_bwd))
+        o.final_state = _ptr(final_state)
+        if counters is not None:
+            o.counters = ctypes.cast(c_void_p(counters.data_ptr()), POINTER(c_uint32))
+        L.check(self.lib.cord_rollout(self._h, _ptr(s0), _ptr(u), _ptr(traj), _ptr(status), byref(o), _stream()))
+        return traj
+
+    def backward(self, u, traj, traj_bar=None, sT_bar=None, store: int = L.STORE_FULL, ckpt_every: int = 10,
+                 status=None, counters=None, use_kappa_bwd=False):
+        s0_bar = self._empty(self.info.s_floats)
+        u_bar = self._empty(max(self.info.u_floats, 1))
+        o = L.BackwardOpts()
+        o.store, o.ckpt_every, o.use_kappa_bwd = store, ckpt_every, int(bool(use_kappa_bwd))
+        o.sT_bar = _ptr(sT_bar)
+        if counters is not None:
+            o.counters = ctypes.cast(c_void_p(counters.data_ptr()), POINTER(c_uint32))
+        L.check(self.lib.cord_rollout_backward(self._h, _ptr(u), _ptr(traj), _ptr(traj_bar), _ptr(s0_bar),
+                                               _ptr(u_bar), _ptr(status), byref(o), _stream()))
+        return s0_bar, u_bar[:self.info.u_floats]
+
+    def linearize(self, traj, u, dense: bool = True, want_B: bool = True, jvp_k: int = 0, jvp_ds=None,
+                  jvp_du=None, status=None, A=None, Bm=None):
+        if dense and A is None:
+            A = self._empty(self.info.A_floats)
+        if want_B and Bm is None:
+            Bm = self._empty(max(self.info.B_floats, 1))
+        jv = None
+        out = None
+        if jvp_k:
+            tns = sum(T * ns for T, ns in zip(self.T, self.n_s))
+            out = self._empty(jvp_k * tns)
+            jv = L.Jvp()
+            jv.k, jv.ds, jv.du, jv.out = jvp_k, _ptr(jvp_ds), _ptr(jvp_du), _ptr(out)
+        L.check(self.lib.cord_linearize(self._h, _ptr(traj), _ptr(u), _ptr(A if dense else None),
+                                        _ptr(Bm if want_B else None), byref(jv) if jv is not None else None,
+                                        _ptr(status), _stream()))
+        return (A if dense else None), (Bm if want_B else None), out
+
+    # ------------------------------------------------------------ helpers
+    def pack_states(self, states):
+        """list of per-instance numpy state vectors -> flat float32 tensor."""
+        return torch.from_numpy(np.concatenate([np.asarray(s, dtype=np.float32).ravel() for s in states])).to(self.device)
+
+    def pack_controls(self, controls):
+        return torch.from_numpy(np.concatenate([np.asarray(u, dtype=np.float32).ravel() for u in controls]
+                                               + [np.zeros(0, np.float32)])).to(self.device)
+
+    def split(self, flat, kind: str, ckpt_every: int = 0):
+        """Split a flat buffer into per-instance numpy arrays (kind: s, u, traj, ckpt, A, B)."""
+        off = self.offsets(ckpt_every)[kind]
+        h = flat.detach().cpu().numpy()
+        return [h[off[i]:off[i + 1]] for i in range(self.B)]

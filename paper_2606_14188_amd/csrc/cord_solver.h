@@ -1,0 +1,1102 @@
+// Device-side solver of one rope/cloth instance per workgroup (gfx950).
+//
+// One workgroup owns one instance for the whole horizon.  Thread t owns the
+// particles p = t + k*NT (k < PPT).  Per-particle state (x, v, the stage-1
+// increment d = q* - x, the stage-2 correction, contact multipliers, the
+// per-spring Hessian data) lives in VGPRs across all time steps; the only
+// vectors that neighbours read (x, d, the CG direction, the stage-2
+// correction) are mirrored in LDS as structure-of-arrays, so neighbour reads
+// of consecutive lanes hit consecutive banks.  HBM is touched only for
+// controls, states/trajectories, cotangents and Jacobian blocks.
+//
+// The step follows Sec. 4.1 of the paper (two-stage solver, contact
+// smoothing); the derivatives follow its "Differentiating Through
+// Simulation" paragraph and eq. (diff-sim).  Design choices that differ from
+// the paper's (dense GPU factorizations in JAX): every linear solve is a
+// matrix-free block-Jacobi preconditioned conjugate gradient whose
+// Hessian-vector product is a nearest-neighbour stencil evaluated from the
+// LDS mirror; reductions are DPP wave reductions plus one LDS exchange.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cord_internal.h"
+
+namespace cord {
+
+// ----------------------------------------------------------------- status
+constexpr int kStOK = 0;
+constexpr int kStNewton = 1;
+constexpr int kStNotPD = 2;
+constexpr int kStQP = 3;
+constexpr int kStNonFinite = 4;
+
+// ----------------------------------------------------------------- solver settings
+constexpr int kNewtonMax = 40;
+constexpr int kLineSearchMax = 30;
+constexpr int kIpmMax = 60;
+constexpr int kPcgMax = 300;
+constexpr float kPcgTolInner = 1e-3f;   // relative residual (preconditioned norm), Newton / IPM
+constexpr float kPcgTolAdj = 1e-6f;     // adjoint / tangent solves
+constexpr float kTolForce = 1e-5f;      // x force scale (m|g| + 1e-3 m/dt^2 h)
+constexpr float kTolGap = 2e-7f;        // x (h + |phi|)
+constexpr float kTolCompl = 1e-5f;      // x kappa
+
+// ----------------------------------------------------------------- reductions
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float rdlane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+// Butterfly inside rows of 16 (quad_perm, half-mirror, mirror), then the
+// four row results via readlane.  Every lane gets the same bits: IEEE
+// addition is commutative, so both partners of a swap compute equal sums.
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp_mov<0xB1>(v);
+    v += dpp_mov<0x4E>(v);
+    v += dpp_mov<0x141>(v);
+    v += dpp_mov<0x140>(v);
+    return (rdlane(v, 0) + rdlane(v, 16)) + (rdlane(v, 32) + rdlane(v, 48));
+}
+__device__ __forceinline__ float wave_max(float v) {
+    v = fmaxf(v, dpp_mov<0xB1>(v));
+    v = fmaxf(v, dpp_mov<0x4E>(v));
+    v = fmaxf(v, dpp_mov<0x141>(v));
+    v = fmaxf(v, dpp_mov<0x140>(v));
+    return fmaxf(fmaxf(rdlane(v, 0), rdlane(v, 16)), fmaxf(rdlane(v, 32), rdlane(v, 48)));
+}
+__device__ __forceinline__ float wave_min(float v) {
+    v = fminf(v, dpp_mov<0xB1>(v));
+    v = fminf(v, dpp_mov<0x4E>(v));
+    v = fminf(v, dpp_mov<0x141>(v));
+    v = fminf(v, dpp_mov<0x140>(v));
+    return fminf(fminf(rdlane(v, 0), rdlane(v, 16)), fminf(rdlane(v, 32), rdlane(v, 48)));
+}
+
+// NaN-propagating max inside a thread.  fmaxf drops NaNs, so before a wave
+// reduction a non-finite value is mapped to the sentinel kBad (finite and
+// larger than any real residual); a reduced value >= kBad means some lane
+// held a NaN or Inf.
+constexpr float kBad = 3.0e38f;
+__device__ __forceinline__ float nmax(float a, float b) { return (a != a || b != b) ? __int_as_float(0x7fc00000) : fmaxf(a, b); }
+__device__ __forceinline__ float finite_key(float a) { return (a == a && a < kBad) ? a : kBad; }
+
+// ----------------------------------------------------------------- 3x3 symmetric helpers
+// (a b c; b d e; c e f) stored as {a, b, c, d, e, f}
+__device__ __forceinline__ void sym_inv(const float m[6], float o[6]) {
+    const float a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5];
+    const float c00 = d * f - e * e, c01 = c * e - b * f, c02 = b * e - c * d;
+    const float c11 = a * f - c * c, c12 = b * c - a * e, c22 = a * d - b * b;
+    const float det = a * c00 + b * c01 + c * c02;
+    const float id = 1.0f / det;
+    o[0] = c00 * id; o[1] = c01 * id; o[2] = c02 * id;
+    o[3] = c11 * id; o[4] = c12 * id; o[5] = c22 * id;
+}
+__device__ __forceinline__ void sym_mul(const float m[6], const float r[3], float o[3]) {
+    o[0] = m[0] * r[0] + m[1] * r[1] + m[2] * r[2];
+    o[1] = m[1] * r[0] + m[3] * r[1] + m[4] * r[2];
+    o[2] = m[2] * r[0] + m[4] * r[1] + m[5] * r[2];
+}
+__device__ __forceinline__ void sym_add_outer(float m[6], float w, const float e[3]) {
+    m[0] += w * e[0] * e[0]; m[1] += w * e[0] * e[1]; m[2] += w * e[0] * e[2];
+    m[3] += w * e[1] * e[1]; m[4] += w * e[1] * e[2]; m[5] += w * e[2] * e[2];
+}
+__device__ __forceinline__ float dot3(const float a[3], const float b[3]) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// ----------------------------------------------------------------- obstacles
+// Signed distance and its gradient (the contact normal).  Ground z = 0;
+// sphere |y - c| - r; rounded box with b = |y - c| - (h - rho):
+// |max(b,0)| - rho outside, max_i b_i - rho inside (ties -> lowest axis).
+__device__ __forceinline__ void sdf_eval(int type, const float* ob, const float y[3], float& phi, float n[3]) {
+    if (type == kObsGround) {
+        phi = y[2]; n[0] = 0.f; n[1] = 0.f; n[2] = 1.f;
+    } else if (type == kObsSphere) {
+        float q[3] = {y[0] - ob[0], y[1] - ob[1], y[2] - ob[2]};
+        float L = sqrtf(dot3(q, q));
+        phi = L - ob[3];
+        if (L > 0.f) { float il = 1.0f / L; n[0] = q[0] * il; n[1] = q[1] * il; n[2] = q[2] * il; }
+        else { n[0] = 0.f; n[1] = 0.f; n[2] = 1.f; }
+    } else {
+        float s[3], b[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float q = y[c] - ob[c];
+            s[c] = q >= 0.f ? 1.f : -1.f;
+            b[c] = s[c] * q - (ob[3 + c] - ob[6]);
+        }
+        if (b[0] > 0.f || b[1] > 0.f || b[2] > 0.f) {
+            float m[3] = {fmaxf(b[0], 0.f), fmaxf(b[1], 0.f), fmaxf(b[2], 0.f)};
+            float L = sqrtf(dot3(m, m));
+            float il = 1.0f / L;
+            phi = L - ob[6];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) n[c] = s[c] * m[c] * il;
+        } else {
+            // deepest face; ties go to the lowest axis (no dynamic indexing,
+            // which would force the arrays out of registers)
+            int k = 0;
+            float bk = b[0];
+            if (b[1] > bk) { k = 1; bk = b[1]; }
+            if (b[2] > bk) { k = 2; bk = b[2]; }
+            phi = bk - ob[6];
+            n[0] = k == 0 ? s[0] : 0.f;
+            n[1] = k == 1 ? s[1] : 0.f;
+            n[2] = k == 2 ? s[2] : 0.f;
+        }
+    }
+}
+
+// Hessian of the signed distance (curvature of the contact normal).
+__device__ __forceinline__ void sdf_hess(int type, const float* ob, const float y[3], float H[6]) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) H[i] = 0.f;
+    if (type == kObsSphere) {
+        float q[3] = {y[0] - ob[0], y[1] - ob[1], y[2] - ob[2]};
+        float L = sqrtf(dot3(q, q));
+        if (L > 0.f) {
+            float il = 1.0f / L;
+            float n[3] = {q[0] * il, q[1] * il, q[2] * il};
+            H[0] = (1.f - n[0] * n[0]) * il; H[1] = -n[0] * n[1] * il; H[2] = -n[0] * n[2] * il;
+            H[3] = (1.f - n[1] * n[1]) * il; H[4] = -n[1] * n[2] * il; H[5] = (1.f - n[2] * n[2]) * il;
+        }
+    } else if (type == kObsBox) {
+        float s[3], b[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float q = y[c] - ob[c];
+            s[c] = q >= 0.f ? 1.f : -1.f;
+            b[c] = s[c] * q - (ob[3 + c] - ob[6]);
+        }
+        if (b[0] > 0.f || b[1] > 0.f || b[2] > 0.f) {
+            float pm[3] = {b[0] > 0.f ? 1.f : 0.f, b[1] > 0.f ? 1.f : 0.f, b[2] > 0.f ? 1.f : 0.f};
+            float m[3] = {fmaxf(b[0], 0.f), fmaxf(b[1], 0.f), fmaxf(b[2], 0.f)};
+            float L = sqrtf(dot3(m, m));
+            float il = 1.0f / L;
+            float mh[3] = {m[0] * il, m[1] * il, m[2] * il};
+            float ds[3] = {s[0] * pm[0], s[1] * pm[1], s[2] * pm[2]};
+            H[0] = ds[0] * ds[0] * (pm[0] - mh[0] * mh[0]) * il;
+            H[1] = ds[0] * ds[1] * (-mh[0] * mh[1]) * il;
+            H[2] = ds[0] * ds[2] * (-mh[0] * mh[2]) * il;
+            H[3] = ds[1] * ds[1] * (pm[1] - mh[1] * mh[1]) * il;
+            H[4] = ds[1] * ds[2] * (-mh[1] * mh[2]) * il;
+            H[5] = ds[2] * ds[2] * (pm[2] - mh[2] * mh[2]) * il;
+        }
+    }
+}
+
+// ----------------------------------------------------------------- topology
+// Spring slots of a particle.  Rope: neighbours +1, -1.  Cloth (node
+// (ix, iy) = iy*nx + ix): structural (+-1,0),(0,+-1); shear (+-1,+-1);
+// bend (+-2,0),(0,+-2).
+template <int TOPO> struct Topo;
+template <> struct Topo<kRope> {
+    static constexpr int NS = 2;
+    __device__ static constexpr int dx(int s) { return s == 0 ? 1 : -1; }
+    __device__ static constexpr int dy(int) { return 0; }
+    __device__ static constexpr int type(int) { return 0; }
+};
+template <> struct Topo<kCloth> {
+    static constexpr int NS = 12;
+    __device__ static constexpr int dx(int s) {
+        return s == 0 ? 1 : s == 1 ? -1 : s == 4 ? 1 : s == 5 ? -1 : s == 6 ? 1 : s == 7 ? -1 : s == 8 ? 2 : s == 9 ? -2 : 0;
+    }
+    __device__ static constexpr int dy(int s) {
+        return s == 2 ? 1 : s == 3 ? -1 : s == 4 ? 1 : s == 5 ? -1 : s == 6 ? -1 : s == 7 ? 1 : s == 10 ? 2 : s == 11 ? -2 : 0;
+    }
+    __device__ static constexpr int type(int s) { return s < 4 ? 0 : s < 8 ? 1 : 2; }
+};
+
+// LDS floats used by one workgroup.
+template <int NT, int PPT>
+constexpr int lds_floats() { return 12 * NT * PPT + 64; }
+
+// ----------------------------------------------------------------- solver
+template <int TOPO, int NT, int PPT, int NOBS>
+struct Solver {
+    static constexpr int NM = NT * PPT;
+    static constexpr int NS = Topo<TOPO>::NS;
+    using TP = Topo<TOPO>;
+
+    // LDS mirrors (SoA, component c at offset c*NM)
+    float* X;    // positions at step start
+    float* D;    // stage-1 increment d = q* - x
+    float* V;    // exchange vector (CG direction, adjoints, tangents)
+    float* DL;   // stage-2 correction / line-search step
+    float* rb;   // reduction scratch (2 x 16)
+    int rslot;
+
+    // instance constants
+    int n, nx, ny, ngrip, nobs;
+    float h, mass, dt, gam, mdt2, kb, tolF, fscale;
+    float g[3];
+    float kS[3], rS[3];
+    int otype[NOBS];
+    float ob[NOBS][7];
+
+    // particles
+    int grip[PPT];          // -1 free, else gripper index; -2 inactive slot
+    int px[PPT], py[PPT];   // grid coordinates (cloth)
+    float x[PPT][3], v[PPT][3], d[PPT][3], dl[PPT][3], ug[PPT][3];
+    float se[PPT][NS][3], sa[PPT][NS], sb[PPT][NS];
+    float Bd[PPT][6], Mi[PPT][6];
+    float cn[PPT][NOBS][3], cphi[PPT][NOBS], clam[PPT][NOBS], cgap[PPT][NOBS];
+
+    int status;
+    uint32_t cnt[4];   // Newton its, PCG its, interior-point its, steps
+
+    __device__ __forceinline__ int pidx(int k) const { return (int)threadIdx.x + k * NT; }
+    __device__ __forceinline__ bool active(int k) const { return grip[k] != -2; }
+    __device__ __forceinline__ bool isfree(int k) const { return grip[k] == -1; }
+
+    __device__ __forceinline__ void init(const InstDev& I, float* lds) {
+        X = lds; D = X + 3 * NM; V = D + 3 * NM; DL = V + 3 * NM; rb = DL + 3 * NM; rslot = 0;
+        n = I.n; nx = I.nx; ny = I.ny; ngrip = I.n_grip; nobs = I.n_obs;
+        h = I.h; mass = I.mass; dt = I.dt; gam = I.gamma; mdt2 = I.mass / (I.dt * I.dt);
+        kb = (TOPO == kRope) ? I.k_bend : 0.f;
+        g[0] = I.g0; g[1] = I.g1; g[2] = I.g2;
+        kS[0] = I.k_struct; kS[1] = I.k_shear; kS[2] = I.k_bend;
+        rS[0] = I.h; rS[1] = I.h * 1.41421356237309515f; rS[2] = 2.f * I.h;
+        // force scale: the weight of a node plus the inertial force of a
+        // 1e-3 h displacement in one step
+        float gn = fmaxf(fabsf(g[0]), fmaxf(fabsf(g[1]), fabsf(g[2])));
+        fscale = mass * gn + 1e-3f * mdt2 * h;
+        tolF = kTolForce * fscale;
+#pragma unroll
+        for (int o = 0; o < NOBS; ++o) {
+            otype[o] = I.obs_type[o];
+#pragma unroll
+            for (int c = 0; c < 7; ++c) ob[o][c] = I.obs[o][c];
+        }
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            int p = pidx(k);
+            int gk = (p < n) ? -1 : -2;
+            for (int j = 0; j < I.n_grip; ++j)
+                if (I.grip_node[j] == p) gk = j;
+            grip[k] = gk;
+            px[k] = (TOPO == kCloth) ? p % nx : p;
+            py[k] = (TOPO == kCloth) ? p / nx : 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { x[k][c] = 0.f; v[k][c] = 0.f; d[k][c] = 0.f; dl[k][c] = 0.f; ug[k][c] = 0.f; }
+        }
+        status = kStOK;
+        cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0;
+    }
+
+    __device__ __forceinline__ void sync() { __syncthreads(); }
+
+    // -------------------------------------------------- block reductions
+    __device__ __forceinline__ float bsum(float v) {
+        v = wave_sum(v);
+        if constexpr (NT == 64) return v;
+        float* b = rb + (rslot & 1) * 16; ++rslot;
+        if ((threadIdx.x & 63) == 0) b[threadIdx.x >> 6] = v;
+        sync();
+        float r = b[0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) r += b[w];
+        return r;
+    }
+    __device__ __forceinline__ float bmax(float v) {
+        v = wave_max(v);
+        if constexpr (NT == 64) return v;
+        float* b = rb + (rslot & 1) * 16; ++rslot;
+        if ((threadIdx.x & 63) == 0) b[threadIdx.x >> 6] = v;
+        sync();
+        float r = b[0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) r = fmaxf(r, b[w]);
+        return r;
+    }
+    __device__ __forceinline__ float bmin(float v) {
+        v = wave_min(v);
+        if constexpr (NT == 64) return v;
+        float* b = rb + (rslot & 1) * 16; ++rslot;
+        if ((threadIdx.x & 63) == 0) b[threadIdx.x >> 6] = v;
+        sync();
+        float r = b[0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) r = fminf(r, b[w]);
+        return r;
+    }
+
+    // -------------------------------------------------- LDS mirrors
+    __device__ __forceinline__ void put(float* A, int k, const float val[3]) {
+        int p = pidx(k);
+        A[p] = val[0]; A[NM + p] = val[1]; A[2 * NM + p] = val[2];
+    }
+    __device__ __forceinline__ void get(const float* A, int q, float out[3]) const {
+        out[0] = A[q]; out[1] = A[NM + q]; out[2] = A[2 * NM + q];
+    }
+    // Publish a per-particle vector (zero on gripped / inactive slots unless
+    // keep_grip).  `presync` = false only where a block reduction (with its
+    // barrier) already separates the last reads of A from this write.
+    __device__ __forceinline__ void publish(float* A, const float val[PPT][3], bool keep_grip = false, bool presync = true) {
+        if (presync || NT == 64) sync();
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            float z[3] = {0.f, 0.f, 0.f};
+            put(A, k, (isfree(k) || (keep_grip && active(k))) ? val[k] : z);
+        }
+        sync();
+    }
+
+    // neighbour of owned particle k (index p) in spring slot s, or -1
+    __device__ __forceinline__ int nbr(int k, int p, int s) const {
+        if constexpr (TOPO == kRope) {
+            int q = p + TP::dx(s);
+            return (q >= 0 && q < n) ? q : -1;
+        } else {
+            int jx = px[k] + TP::dx(s), jy = py[k] + TP::dy(s);
+            return (jx >= 0 && jx < nx && jy >= 0 && jy < ny) ? p + TP::dx(s) + TP::dy(s) * nx : -1;
+        }
+    }
+
+    // -------------------------------------------------- state I/O
+    __device__ __forceinline__ void load_state(const float* s) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            int p = pidx(k);
+            if (active(k)) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { x[k][c] = s[3 * p + c]; v[k][c] = s[3 * n + 3 * p + c]; }
+            }
+        }
+    }
+    __device__ __forceinline__ void store_state(float* s) const {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            int p = pidx(k);
+            if (active(k)) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { s[3 * p + c] = x[k][c]; s[3 * n + 3 * p + c] = v[k][c]; }
+            }
+        }
+    }
+
+    // -------------------------------------------------- stage-1 pieces
+    // Gradient F of the incremental potential at y = x + d and the spring
+    // Hessian data: K_s w = sa e (e.w) + sb w with sa = k(1 - f), sb = k f,
+    // f = 1 - l0/L, clamped at 0 when `project`.  Also the diagonal 3x3 block
+    // of the Hessian in Bd.  Gripped particles get F = 0 (the cache is still
+    // filled: their rows are needed by the backward pass).
+    __device__ __forceinline__ void grad_cache(bool project, float F[PPT][3]) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int p = pidx(k);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) F[k][c] = 0.f;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) Bd[k][i] = 0.f;
+            Bd[k][0] = Bd[k][3] = Bd[k][5] = mdt2;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) { sa[k][s] = 0.f; sb[k][s] = 0.f; se[k][s][0] = se[k][s][1] = se[k][s][2] = 0.f; }
+            if (!active(k)) continue;
+            if (isfree(k)) {
+                const float cv = dt * (1.f - gam);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) F[k][c] = mdt2 * (d[k][c] - cv * v[k][c]) - mass * g[c];
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int q = nbr(k, p, s);
+                if (q < 0) continue;
+                const int ty = TP::type(s);
+                const float kk = kS[ty], l0 = rS[ty];
+                float e[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) e[c] = (X[c * NM + q] - x[k][c]) + (D[c * NM + q] - d[k][c]);
+                const float L = sqrtf(dot3(e, e));
+                const float il = 1.0f / L;
+                float eh[3] = {e[0] * il, e[1] * il, e[2] * il};
+                const float f = 1.f - l0 * il;
+                const float fr = isfree(k) ? kk * (L - l0) : 0.f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) F[k][c] -= fr * eh[c];
+                const float fp = project ? fmaxf(f, 0.f) : f;
+                sa[k][s] = kk * (1.f - fp);
+                sb[k][s] = kk * fp;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) se[k][s][c] = eh[c];
+                sym_add_outer(Bd[k], sa[k][s], eh);
+                Bd[k][0] += sb[k][s]; Bd[k][3] += sb[k][s]; Bd[k][5] += sb[k][s];
+            }
+            if constexpr (TOPO == kRope) {
+                float wdiag = 0.f;
+#pragma unroll
+                for (int j = -1; j <= 1; ++j) {
+                    const int cc = p + j;
+                    if (cc < 1 || cc > n - 2) continue;
+                    const float w = (j == 0) ? -2.f : 1.f;
+                    wdiag += w * w;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const float kap = (X[c * NM + cc - 1] - 2.f * X[c * NM + cc] + X[c * NM + cc + 1]) +
+                                          (D[c * NM + cc - 1] - 2.f * D[c * NM + cc] + D[c * NM + cc + 1]);
+                        if (isfree(k)) F[k][c] += w * kb * kap;
+                    }
+                }
+                Bd[k][0] += kb * wdiag; Bd[k][3] += kb * wdiag; Bd[k][5] += kb * wdiag;
+            }
+        }
+    }
+
+    // Hessian-vector product with the vector mirrored in V.  Rows of free
+    // particles: (M/dt^2) w_p + sum_s K_s (w_p - w_q) + bending stencil
+    // (+ contact weights if CONTACT).  With `grip_rows`, gripped particles get
+    // their elastic row (no mass term), else 0.
+    template <bool CONTACT>
+    __device__ __forceinline__ void apply(float q[PPT][3], bool grip_rows = false, bool with_mass = true) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int p = pidx(k);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) q[k][c] = 0.f;
+            if (!active(k)) continue;
+            if (!isfree(k) && !grip_rows) continue;
+            float wp[3];
+            get(V, p, wp);
+            if (isfree(k) && with_mass) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) q[k][c] = mdt2 * wp[c];
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int nq = nbr(k, p, s);
+                if (nq < 0) continue;
+                float wq[3];
+                get(V, nq, wq);
+                float dv[3] = {wp[0] - wq[0], wp[1] - wq[1], wp[2] - wq[2]};
+                const float t = sa[k][s] * dot3(se[k][s], dv);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) q[k][c] += t * se[k][s][c] + sb[k][s] * dv[c];
+            }
+            if constexpr (TOPO == kRope) {
+#pragma unroll
+                for (int j = -1; j <= 1; ++j) {
+                    const int cc = p + j;
+                    if (cc < 1 || cc > n - 2) continue;
+                    const float w = ((j == 0) ? -2.f : 1.f) * kb;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        q[k][c] += w * (V[c * NM + cc - 1] - 2.f * V[c * NM + cc] + V[c * NM + cc + 1]);
+                }
+            }
+            if constexpr (CONTACT) {
+                if (isfree(k)) {
+#pragma unroll
+                    for (int o = 0; o < NOBS; ++o) {
+                        if (o >= nobs) continue;
+                        const float w = clam[k][o] / cgap[k][o] * dot3(cn[k][o], wp);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) q[k][c] += w * cn[k][o][c];
+                    }
+                }
+            }
+        }
+    }
+
+    // block-Jacobi preconditioner from Bd (+ contact weights)
+    template <bool CONTACT>
+    __device__ __forceinline__ void build_precond() {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            float m[6];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) m[i] = Bd[k][i];
+            if constexpr (CONTACT) {
+#pragma unroll
+                for (int o = 0; o < NOBS; ++o)
+                    if (o < nobs) sym_add_outer(m, clam[k][o] / cgap[k][o], cn[k][o]);
+            }
+            if (isfree(k)) sym_inv(m, Mi[k]);
+            else {
+#pragma unroll
+                for (int i = 0; i < 6; ++i) Mi[k][i] = 0.f;
+            }
+        }
+    }
+
+    // Preconditioned conjugate gradients on the free DoFs.  Returns false if
+    // non-positive curvature was met (the iterate so far is kept).
+    template <bool CONTACT>
+    __device__ __forceinline__ bool pcg(const float b[PPT][3], float xs[PPT][3], float rtol) {
+        float r[PPT][3], z[PPT][3], pp[PPT][3], q[PPT][3];
+        float rz = 0.f;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { xs[k][c] = 0.f; r[k][c] = isfree(k) ? b[k][c] : 0.f; }
+            sym_mul(Mi[k], r[k], z[k]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pp[k][c] = z[k][c];
+            rz += dot3(r[k], z[k]);
+        }
+        rz = bsum(rz);
+        const float rz0 = rz;
+        if (!(rz0 > 0.f)) return rz0 == 0.f;
+        bool ok = true;
+        for (int it = 0; it < kPcgMax; ++it) {
+            publish(V, pp, false, false);
+            apply<CONTACT>(q);
+            float pq = 0.f;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) pq += dot3(pp[k], q[k]);
+            pq = bsum(pq);
+            ++cnt[1];
+            if (!(pq > 0.f)) { ok = false; break; }
+            const float alpha = rz / pq;
+            float rzn = 0.f;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { xs[k][c] += alpha * pp[k][c]; r[k][c] -= alpha * q[k][c]; }
+                sym_mul(Mi[k], r[k], z[k]);
+                rzn += dot3(r[k], z[k]);
+            }
+            rzn = bsum(rzn);
+            if (!(rzn > rtol * rtol * rz0)) break;
+            const float beta = rzn / rz;
+            rz = rzn;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) pp[k][c] = z[k][c] + beta * pp[k][c];
+        }
+        return ok;
+    }
+
+    // Psi(y + DL) - Psi(y) with DL mirrored in LDS, in cancellation-free form
+    // (each spring counted half at each end, each bending triplet at its
+    // centre, inertia and gravity at free particles).
+    __device__ __forceinline__ float psi_diff() {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int p = pidx(k);
+            if (!active(k)) continue;
+            float sp[3];
+            get(DL, p, sp);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int q = nbr(k, p, s);
+                if (q < 0) continue;
+                const int ty = TP::type(s);
+                float e0[3], de[3], e1[3], sm[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    e0[c] = (X[c * NM + q] - x[k][c]) + (D[c * NM + q] - d[k][c]);
+                    de[c] = DL[c * NM + q] - sp[c];
+                    e1[c] = e0[c] + de[c];
+                    sm[c] = e1[c] + e0[c];
+                }
+                const float L0 = sqrtf(dot3(e0, e0)), L1 = sqrtf(dot3(e1, e1));
+                const float dL = dot3(de, sm) / (L1 + L0);
+                acc += 0.25f * kS[ty] * dL * (L1 + L0 - 2.f * rS[ty]);
+            }
+            if constexpr (TOPO == kRope) {
+                if (p >= 1 && p <= n - 2) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const float k0 = (X[c * NM + p - 1] - 2.f * X[c * NM + p] + X[c * NM + p + 1]) +
+                                         (D[c * NM + p - 1] - 2.f * D[c * NM + p] + D[c * NM + p + 1]);
+                        const float dk = DL[c * NM + p - 1] - 2.f * DL[c * NM + p] + DL[c * NM + p + 1];
+                        acc += 0.5f * kb * dk * (2.f * k0 + dk);
+                    }
+                }
+            }
+            if (isfree(k)) {
+                const float cv = dt * (1.f - gam);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    acc += 0.5f * mdt2 * sp[c] * (2.f * (d[k][c] - cv * v[k][c]) + sp[c]) - mass * g[c] * sp[c];
+            }
+        }
+        return bsum(acc);
+    }
+
+    // -------------------------------------------------- one step
+    // Grippers and predictor; publishes x and d.
+    __device__ __forceinline__ void begin_step(const float* ut) {
+        sync();
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (!active(k)) continue;
+            if (grip[k] >= 0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { ug[k][c] = ut[3 * grip[k] + c]; d[k][c] = dt * ug[k][c]; }
+            } else {
+                // Newton starts from the predictor plus the free-fall drop
+                // dt^2 g (the root does not depend on the start)
+                const float cv = dt * (1.f - gam);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) d[k][c] = cv * v[k][c] + dt * dt * g[c];
+            }
+            put(X, k, x[k]);
+            put(D, k, d[k]);
+        }
+        sync();
+    }
+
+    // Stage 1: Newton on F(y) = 0 (minimising Psi), projected-Hessian
+    // directions, Armijo backtracking on Psi.
+    __device__ __forceinline__ void stage1() {
+        float F[PPT][3], del[PPT][3];
+        bool conv = false;
+        float fmax = 0.f;
+        for (int it = 0; it < kNewtonMax; ++it) {
+            grad_cache(true, F);
+            float lm = 0.f;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) lm = nmax(lm, fabsf(F[k][c]));
+            fmax = bmax(finite_key(lm));
+            if (fmax >= kBad) { status = max(status, kStNonFinite); return; }
+            if (fmax <= tolF) { conv = true; break; }
+            build_precond<false>();
+            float rhs[PPT][3];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rhs[k][c] = -F[k][c];
+            pcg<false>(rhs, del, kPcgTolInner);
+            ++cnt[0];
+            float gtd = 0.f;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) gtd += dot3(F[k], del[k]);
+            gtd = bsum(gtd);
+            if (!(gtd < 0.f)) break;
+            float alpha = 1.f;
+            bool acc = false;
+            float stp[PPT][3];
+            for (int ls = 0; ls < kLineSearchMax; ++ls) {
+#pragma unroll
+                for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) stp[k][c] = alpha * del[k][c];
+                publish(DL, stp);
+                const float dpsi = psi_diff();
+                if (dpsi <= 1e-4f * alpha * gtd) { acc = true; break; }
+                alpha *= 0.5f;
+            }
+            if (!acc) break;
+            float smax = 0.f;
+            if constexpr (NT == 64) sync();
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                if (isfree(k)) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { d[k][c] += stp[k][c]; smax = fmaxf(smax, fabsf(stp[k][c])); }
+                    put(D, k, d[k]);
+                }
+            }
+            sync();
+            smax = bmax(finite_key(smax));
+            if (smax <= 1e-7f * h) { conv = fmax <= 100.f * tolF; break; }
+        }
+        if (!conv) {
+            grad_cache(true, F);
+            float lm = 0.f;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) lm = nmax(lm, fabsf(F[k][c]));
+            fmax = bmax(finite_key(lm));
+            if (fmax >= kBad) status = max(status, kStNonFinite);
+            else if (!(fmax <= 100.f * tolF)) status = max(status, kStNewton);
+        }
+    }
+
+    // Contact pairs at y* = x + d for every (free particle, obstacle).
+    __device__ __forceinline__ void eval_contacts() {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            float y[3] = {x[k][0] + d[k][0], x[k][1] + d[k][1], x[k][2] + d[k][2]};
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) {
+                if (o < nobs && isfree(k)) sdf_eval(otype[o], ob[o], y, cphi[k][o], cn[k][o]);
+                else { cphi[k][o] = 1.f; cn[k][o][0] = cn[k][o][1] = cn[k][o][2] = 0.f; }
+            }
+        }
+    }
+
+    // Stage 2 (eq. dynamics-second-stage with the smoothed complementarity):
+    // P D = sum_c n_c lam_c, lam_c gap_c = mu, gap_c = phi_c + n_c . D_p,
+    // solved by a primal-dual interior point from an infeasible start.
+    // kappa > 0: mu = kappa.  kappa = 0: mu is driven towards 0 (hard contact).
+    __device__ __forceinline__ void stage2(float kappa) {
+        float F[PPT][3];
+        grad_cache(false, F);      // exact Hessian data at y*
+        eval_contacts();
+        const bool hard = !(kappa > 0.f);
+        // initial point: each pair as if alone with stiffness n^T P_pp n
+        float mu = kappa;
+        if (hard) {
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                for (int o = 0; o < NOBS; ++o)
+                    if (o < nobs && isfree(k)) {
+                        float t[3];
+                        sym_mul(Bd[k], cn[k][o], t);
+                        acc += dot3(cn[k][o], t) * cphi[k][o] * cphi[k][o];
+                    }
+            acc = bsum(acc);
+            int np = 0;
+            np = (n - ngrip) * nobs;
+            mu = fmaxf(1e-2f * acc / fmaxf((float)np, 1.f), 1e-9f * fscale * h);
+        }
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dl[k][c] = 0.f;
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) {
+                float t[3];
+                sym_mul(Bd[k], cn[k][o], t);
+                const float pi = fmaxf(dot3(cn[k][o], t), mdt2);
+                const float ph = cphi[k][o];
+                const float gp = 0.5f * (ph + sqrtf(ph * ph + 4.f * mu / pi));
+                cgap[k][o] = (o < nobs && isfree(k)) ? gp : 1.f;
+                clam[k][o] = (o < nobs && isfree(k)) ? mu / gp : 0.f;
+            }
+        }
+        if (nobs == 0) return;
+        const float mu_min = 1e-7f * fscale * h;
+        bool conv = false;
+        for (int it = 0; it < kIpmMax; ++it) {
+            float rd[PPT][3];
+            publish(V, dl);
+            apply<false>(rd);
+            float err = 0.f, comp = 0.f;
+            float rp[PPT][NOBS], rc[PPT][NOBS];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+                for (int o = 0; o < NOBS; ++o) {
+                    rp[k][o] = 0.f; rc[k][o] = 0.f;
+                    if (o < nobs && isfree(k)) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) rd[k][c] -= cn[k][o][c] * clam[k][o];
+                        rp[k][o] = cgap[k][o] - cphi[k][o] - dot3(cn[k][o], dl[k]);
+                        comp += clam[k][o] * cgap[k][o];
+                        err = nmax(err, fabsf(rp[k][o]) / (kTolGap * (h + fabsf(cphi[k][o]))));
+                    }
+                }
+                if (isfree(k))
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) err = nmax(err, fabsf(rd[k][c]) / tolF);
+            }
+            float mtarget = mu;
+            if (hard) {
+                float cs = bsum(comp);
+                mtarget = fmaxf(0.1f * cs / fmaxf((float)((n - ngrip) * nobs), 1.f), mu_min);
+            }
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                for (int o = 0; o < NOBS; ++o)
+                    if (o < nobs && isfree(k)) {
+                        rc[k][o] = clam[k][o] * cgap[k][o] - mtarget;
+                        if (!hard) err = nmax(err, fabsf(rc[k][o]) / (kTolCompl * kappa));
+                        else err = nmax(err, clam[k][o] * cgap[k][o] / (10.f * mu_min));
+                    }
+            err = bmax(finite_key(err));
+            if (err >= kBad) { status = max(status, kStNonFinite); return; }
+            if (err <= 1.f) { conv = true; break; }
+            float rhs[PPT][3], dD[PPT][3];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rhs[k][c] = -rd[k][c];
+#pragma unroll
+                for (int o = 0; o < NOBS; ++o)
+                    if (o < nobs && isfree(k)) {
+                        const float w = (-rc[k][o] + clam[k][o] * rp[k][o]) / cgap[k][o];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) rhs[k][c] += w * cn[k][o][c];
+                    }
+            }
+            build_precond<true>();
+            pcg<true>(rhs, dD, kPcgTolInner);
+            ++cnt[2];
+            float amax = 1.f / 0.995f;
+            float dg[PPT][NOBS], dlm[PPT][NOBS];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                for (int o = 0; o < NOBS; ++o) {
+                    dg[k][o] = 0.f; dlm[k][o] = 0.f;
+                    if (o < nobs && isfree(k)) {
+                        dg[k][o] = dot3(cn[k][o], dD[k]) - rp[k][o];
+                        dlm[k][o] = (-rc[k][o] - clam[k][o] * dg[k][o]) / cgap[k][o];
+                        if (dg[k][o] < 0.f) amax = fminf(amax, -cgap[k][o] / dg[k][o]);
+                        if (dlm[k][o] < 0.f) amax = fminf(amax, -clam[k][o] / dlm[k][o]);
+                    }
+                }
+            amax = bmin(amax);
+            const float alpha = fminf(1.f, 0.995f * amax);
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) dl[k][c] += alpha * dD[k][c];
+#pragma unroll
+                for (int o = 0; o < NOBS; ++o)
+                    if (o < nobs && isfree(k)) { cgap[k][o] += alpha * dg[k][o]; clam[k][o] += alpha * dlm[k][o]; }
+            }
+        }
+        if (!conv) status = max(status, kStQP);
+    }
+
+    // Full step at relaxation kappa: stages 1 and 2 (state not advanced).
+    __device__ __forceinline__ void solve_step(const float* ut, float kappa) {
+        begin_step(ut);
+        stage1();
+        stage2(kappa);
+        publish(DL, dl);   // stage-2 correction mirrored for the derivatives
+        ++cnt[3];
+    }
+
+    // x <- x+, v <- v+  (free: x + (d + D), (d + D)/dt; gripped: x + dt u, u)
+    __device__ __forceinline__ void advance() {
+        const float idt = 1.0f / dt;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (!active(k)) continue;
+            if (isfree(k)) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float inc = d[k][c] + dl[k][c];
+                    x[k][c] = x[k][c] + inc;
+                    v[k][c] = inc * idt;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { x[k][c] = x[k][c] + dt * ug[k][c]; v[k][c] = ug[k][c]; }
+            }
+        }
+    }
+
+    // -------------------------------------------------- derivatives
+    // (W w)_p = sum_s W_s (w_p - w_q), W_s = k l0/L^3 [(e.De) I + De e^T +
+    // e De^T - 3 (e.De) e_hat e_hat^T], De = D_q - D_p (third derivative of
+    // the spring energy contracted with the stage-2 correction).  The vector
+    // w is mirrored in V, the correction in DL, y* = X + D.
+    __device__ __forceinline__ void apply_third(float q[PPT][3], bool grip_rows) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int p = pidx(k);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) q[k][c] = 0.f;
+            if (!active(k) || (!isfree(k) && !grip_rows)) continue;
+            float wp[3], Dp[3];
+            get(V, p, wp);
+            get(DL, p, Dp);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int nq = nbr(k, p, s);
+                if (nq < 0) continue;
+                const int ty = TP::type(s);
+                float e[3], De[3], we[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    e[c] = (X[c * NM + nq] - x[k][c]) + (D[c * NM + nq] - d[k][c]);
+                    De[c] = DL[c * NM + nq] - Dp[c];
+                    we[c] = wp[c] - V[c * NM + nq];
+                }
+                const float L2 = dot3(e, e);
+                const float L = sqrtf(L2);
+                const float il = 1.0f / L;
+                const float cw = kS[ty] * rS[ty] * il * il * il;
+                const float eD = dot3(e, De), ew = dot3(e, we), Dw = dot3(De, we);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    q[k][c] += cw * (eD * we[c] + De[c] * ew + e[c] * Dw - 3.f * eD * ew * e[c] / L2);
+            }
+        }
+    }
+
+    // VJP of one solved step (eq. diff-sim).  In: xb, vb = cotangents of
+    // (x+, v+).  Out: xb, vb = cotangents of (x, v); ubk = cotangent of the
+    // gripper velocity (gripped particles only); dxb = change of xb.
+    //
+    // With qb = xb + vb/dt, z = K^{-1} qb and mu = P^{-1} (P - W + C - R)^T z
+    // the update is xb <- (M/dt^2) mu - vb/dt, vb <- dt (1-gamma) (M/dt^2) mu.
+    // Both terms of the first carry vb/dt, which grows along the horizon, so
+    // it is evaluated through the increment delta = (M/dt^2) mu - qb:
+    //   P delta = (M/dt^2)(C - W - R^T - N^T Lam N) z - K_el qb
+    // (K_el = P - M/dt^2, the elastic part), xb <- xb + delta,
+    // vb <- dt (1-gamma)(qb + delta): no cancellation of large terms.
+    __device__ __forceinline__ void adjoint(float xb[PPT][3], float vb[PPT][3], float ubk[PPT][3], float kappa,
+                                            float dxb[PPT][3]) {
+        const float idt = 1.0f / dt;
+        float qb[PPT][3], z[PPT][3], e1[PPT][3], del[PPT][3], mu[PPT][3], t1[PPT][3], t2[PPT][3];
+        float bb[PPT][3];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                qb[k][c] = isfree(k) ? xb[k][c] + vb[k][c] * idt : 0.f;
+                bb[k][c] = (active(k) && !isfree(k)) ? xb[k][c] : 0.f;
+            }
+        // stage 2: z = K^{-1} qb, K = P + N^T Lam N
+        build_precond<true>();
+        if (!pcg<true>(qb, z, kPcgTolAdj)) status = max(status, kStNotPD);
+        // e1 = (C - W - R^T - N^T Lam N) z ; gripped rows: bb -= (W z)_g
+        publish(V, z);
+        apply_third(t2, true);
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) e1[k][c] = 0.f;
+            if (!active(k)) continue;
+            if (!isfree(k)) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) bb[k][c] -= t2[k][c];
+                continue;
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) e1[k][c] = -t2[k][c];
+            float yst[3] = {x[k][0] + d[k][0], x[k][1] + d[k][1], x[k][2] + d[k][2]};
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) {
+                if (o >= nobs) continue;
+                float Hc[6], cz[3], hd[3];
+                sdf_hess(otype[o], ob[o], yst, Hc);
+                sym_mul(Hc, z[k], cz);
+                sym_mul(Hc, dl[k], hd);
+                const float w = kappa > 0.f ? clam[k][o] / cgap[k][o] : 0.f;
+                const float nz = dot3(cn[k][o], z[k]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) e1[k][c] += clam[k][o] * cz[c] - w * nz * (hd[c] + cn[k][o][c]);
+            }
+        }
+        // rhs = (M/dt^2) e1 - K_el qb
+        publish(V, qb);
+        apply<false>(t1, false, false);
+        float rhs[PPT][3];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) rhs[k][c] = isfree(k) ? mdt2 * e1[k][c] - t1[k][c] : 0.f;
+        build_precond<false>();
+        if (!pcg<false>(rhs, del, kPcgTolAdj)) status = max(status, kStNotPD);
+        const float imdt2 = 1.0f / mdt2;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) mu[k][c] = isfree(k) ? (qb[k][c] + del[k][c]) * imdt2 : 0.f;
+        publish(V, mu);
+        apply<false>(t1, true);    // gripped rows: (H_gf mu)
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (!active(k)) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { dxb[k][c] = 0.f; ubk[k][c] = 0.f; }
+                continue;
+            }
+            if (isfree(k)) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    dxb[k][c] = del[k][c];
+                    vb[k][c] = dt * (1.f - gam) * (qb[k][c] + del[k][c]);
+                    xb[k][c] += del[k][c];
+                    ubk[k][c] = 0.f;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float tot = bb[k][c] - t1[k][c];
+                    ubk[k][c] = dt * tot + vb[k][c];
+                    dxb[k][c] = tot - xb[k][c];
+                    xb[k][c] = tot;
+                    vb[k][c] = 0.f;
+                }
+            }
+        }
+    }
+
+    // JVP of one solved step: (dx, dv, du) -> (dx+, dv+).  du is this
+    // particle's gripper tangent (gripped particles only).  Written through
+    // increments so that dv+ never forms (dx+ - dx)/dt:
+    //   dxhat = dx + dt (1-gamma) dv,  db = dx_g + dt du,
+    //   H eps = -(K_el dxhat + H_fg db),            dy = dxhat + eps,
+    //   K eta = (C - W - R - N^T Lam N) dy - W_fg db,  dx+ = dy + eta,
+    //   dv+ = (1-gamma) dv + (eps + eta)/dt.
+    __device__ __forceinline__ void tangent(const float dx[PPT][3], const float dv[PPT][3], const float du[PPT][3],
+                                            float ox[PPT][3], float ov[PPT][3], float kappa) {
+        const float idt = 1.0f / dt;
+        float db[PPT][3], xh[PPT][3], r1[PPT][3], eps[PPT][3], dy[PPT][3], t1[PPT][3], t2[PPT][3];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const bool g = active(k) && !isfree(k);
+                db[k][c] = g ? dx[k][c] + dt * du[k][c] : 0.f;
+                xh[k][c] = isfree(k) ? dx[k][c] + dt * (1.f - gam) * dv[k][c] : 0.f;
+            }
+        float full[PPT][3];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) full[k][c] = isfree(k) ? xh[k][c] : db[k][c];
+        publish(V, full, true);
+        apply<false>(t1, false, false);   // K_el dxhat + H_fg db (free rows)
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) r1[k][c] = isfree(k) ? -t1[k][c] : 0.f;
+        build_precond<false>();
+        if (!pcg<false>(r1, eps, kPcgTolAdj)) status = max(status, kStNotPD);
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                dy[k][c] = isfree(k) ? xh[k][c] + eps[k][c] : 0.f;
+                full[k][c] = isfree(k) ? dy[k][c] : db[k][c];
+            }
+        publish(V, full, true);
+        apply_third(t2, false);           // W_ff dy + W_fg db
+        float r2[PPT][3];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) r2[k][c] = isfree(k) ? -t2[k][c] : 0.f;
+            if (!isfree(k)) continue;
+            float yst[3] = {x[k][0] + d[k][0], x[k][1] + d[k][1], x[k][2] + d[k][2]};
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) {
+                if (o >= nobs) continue;
+                float Hc[6], cy[3], hd[3];
+                sdf_hess(otype[o], ob[o], yst, Hc);
+                sym_mul(Hc, dy[k], cy);
+                sym_mul(Hc, dl[k], hd);
+                const float w = kappa > 0.f ? clam[k][o] / cgap[k][o] : 0.f;
+                const float s2 = w * (dot3(hd, dy[k]) + dot3(cn[k][o], dy[k]));
+#pragma unroll
+                for (int c = 0; c < 3; ++c) r2[k][c] += clam[k][o] * cy[c] - s2 * cn[k][o][c];
+            }
+        }
+        float eta[PPT][3];
+        build_precond<true>();
+        if (!pcg<true>(r2, eta, kPcgTolAdj)) status = max(status, kStNotPD);
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (isfree(k)) {
+                    ox[k][c] = dy[k][c] + eta[k][c];
+                    ov[k][c] = (1.f - gam) * dv[k][c] + (eps[k][c] + eta[k][c]) * idt;
+                } else if (active(k)) { ox[k][c] = db[k][c]; ov[k][c] = du[k][c]; }
+                else { ox[k][c] = 0.f; ov[k][c] = 0.f; }
+            }
+    }
+};
+
+}  // namespace cord

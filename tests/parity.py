@@ -1,0 +1,30 @@
+"""Comparison helpers shared by the GPU parity tests.
+
+Tolerances (FP32 GPU vs FP64 oracle, per instance):
+  states      max |dx| / max(|x_or|_inf, 1e-3) <= 1e-4, and the same for the
+              velocity block separately (velocities are differences of
+              positions divided by dt, so a combined norm would hide them);
+  gradients   |g - g_or|_2 / |g_or|_2 <= 1e-3;
+  Jacobians   per step |A - A_or|_F / |A_or|_F <= 1e-3.
+"""
+import numpy as np
+
+STATE_TOL = 1e-4
+GRAD_TOL = 1e-3
+JAC_TOL = 1e-3
+
+
+def state_errors(traj, ref, n):
+    traj = np.asarray(traj, dtype=np.float64).reshape(ref.shape)
+    x, xr = traj[..., :3 * n], ref[..., :3 * n]
+    v, vr = traj[..., 3 * n:], ref[..., 3 * n:]
+    ex = np.max(np.abs(x - xr)) / max(np.max(np.abs(xr)), 1e-3)
+    ev = np.max(np.abs(v - vr)) / max(np.max(np.abs(vr)), 1e-3)
+    return float(ex), float(ev)
+
+
+def rel_l2(g, ref):
+    g = np.asarray(g, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    den = np.linalg.norm(ref)
+    return float(np.linalg.norm(g - ref) / (den if den > 0 else 1.0))

@@ -1,0 +1,93 @@
+"""The C-ABI library loads, exports every symbol include/cord.h declares, its
+struct sizes match the Python mirrors, and descriptor validation rejects bad
+input before touching a device (no GPU compute in this file)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2606_14188_amd import _lib as L
+    return L, L.load()
+
+
+def test_exports_every_declared_symbol():
+    L, lib = _lib()
+    hdr = open(os.path.join(ROOT, "include", "cord.h")).read()
+    names = set(re.findall(r"^\s*(?:int|const char\*)\s+(cord_\w+)\s*\(", hdr, re.M))
+    assert {"cord_sim_create", "cord_rollout", "cord_rollout_backward", "cord_linearize"} <= names
+    for name in sorted(names):
+        assert hasattr(lib, name), name
+    assert set(L._EXPORTS) >= names
+
+
+def test_abi_sizes_match():
+    L, lib = _lib()
+    sizes = (ctypes.c_int64 * 6)()
+    assert lib.cord_abi_sizes(sizes, 6) == 0
+    for st, sz in zip(L._STRUCTS, sizes):
+        assert ctypes.sizeof(st) == sz
+    assert lib.cord_abi_sizes(None, 6) == L.CORD_EINVAL
+
+
+def _create(descs):
+    L, lib = _lib()
+    arr = (L.InstanceDesc * len(descs))(*descs)
+    h = ctypes.c_void_p()
+    rc = lib.cord_sim_create(arr, len(descs), ctypes.byref(h))
+    msg = lib.cord_last_error().decode()
+    if rc == 0:
+        lib.cord_sim_destroy(h)
+    return rc, msg
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("dt", 0.0, 1), ("gamma", 1.5, 1), ("kappa_bwd", 0.0, 1), ("kappa_fwd", -1.0, 1),
+    ("mu", 0.3, 4), ("T", 0, 1), ("mass", 0.0, 1), ("ny", 2, 1), ("grip", 99, 1),
+    ("nspheres", 5, 1), ("n_inst0", 0, 1),
+])
+def test_validation_errors(field, value, code):
+    from paper_2606_14188_amd.api import make_desc
+    L, lib = _lib()
+    d = make_desc(W.config_c1())
+    if field in ("dt", "gamma", "kappa_bwd", "kappa_fwd", "mu"):
+        setattr(d.params, field, value)
+    elif field == "grip":
+        d.grip_node[0] = value
+    elif field == "nspheres":
+        d.n_sphere = value
+    elif field == "n_inst0":
+        arr = (L.InstanceDesc * 1)(d)
+        h = ctypes.c_void_p()
+        assert lib.cord_sim_create(arr, 0, ctypes.byref(h)) == code
+        return
+    else:
+        setattr(d, field, value)
+    rc, msg = _create([d])
+    assert rc == code, msg
+    assert msg
+
+
+def test_too_many_obstacles_unsupported():
+    from paper_2606_14188_amd.api import make_desc
+    inst = W.config_c1()
+    inst = inst.replace(spheres=np.tile(inst.spheres, (4, 1)))
+    d = make_desc(inst)
+    rc, msg = _create([d])
+    assert rc == 4 and "obstacles" in msg
+
+
+def test_null_arguments():
+    L, lib = _lib()
+    assert lib.cord_rollout(None, None, None, None, None, None, None) == L.CORD_EINVAL
+    assert lib.cord_rollout_backward(None, None, None, None, None, None, None, None, None) == L.CORD_EINVAL
+    assert lib.cord_linearize(None, None, None, None, None, None, None, None) == L.CORD_EINVAL
+    assert lib.cord_sim_destroy(None) == 0
+    assert lib.cord_last_error().decode()

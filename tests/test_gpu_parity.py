@@ -1,0 +1,275 @@
+"""GPU parity: libcord (HIP, FP32, through the C ABI) against the FP64 oracle
+on the same seeded inputs.  Sizes span several workgroup tiles and ragged
+tails; full-size configurations are checked on sampled instances."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.derivatives import StepDerivative, rollout_backward
+from oracle.step import rollout as orollout
+from tests.parity import GRAD_TOL, JAC_TOL, STATE_TOL, rel_l2, state_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(insts):
+    from paper_2606_14188_amd import Sim
+    return Sim(insts)
+
+
+def _run(insts, **kw):
+    import torch
+    sim = _sim(insts)
+    s0 = sim.pack_states([i.s0 for i in insts])
+    u = sim.pack_controls([i.u for i in insts])
+    st = torch.full((len(insts),), -1, dtype=torch.int32, device=sim.device)
+    traj = sim.rollout(s0, u, status=st, **kw)
+    torch.cuda.synchronize()
+    return sim, s0, u, traj, st.cpu().numpy()
+
+
+def _check_states(sim, traj, insts, idx=None):
+    parts = sim.split(traj, "traj")
+    idx = range(len(insts)) if idx is None else idx
+    for i in idx:
+        inst = insts[i]
+        ref, st = orollout(inst)
+        assert st.max() == 0
+        ex, ev = state_errors(parts[i], ref, inst.n)
+        print(f"instance {i} ({inst.kind} n={inst.n} T={inst.T}): state err x {ex:.2e} v {ev:.2e}", flush=True)
+        assert ex <= STATE_TOL and ev <= STATE_TOL, (i, ex, ev)
+
+
+def test_c1_forward_and_gradient():
+    import torch
+    inst = W.config_c1()
+    sim, s0, u, traj, st = _run([inst])
+    assert st.tolist() == [0]
+    _check_states(sim, traj, [inst])
+    n = inst.n
+    ref, _ = orollout(inst)
+    d = ref[-1, 3 * (n - 1):3 * n] - W.gen.C1_GOAL
+    sb = np.zeros(6 * n)
+    sb[3 * (n - 1):3 * n] = d / np.linalg.norm(d)
+    s0b_or, ub_or = rollout_backward(inst, ref, sT_bar=sb)
+    sT_bar = torch.tensor(sb, dtype=torch.float32, device=sim.device)
+    s0b, ub = sim.backward(u, traj, sT_bar=sT_bar)
+    torch.cuda.synchronize()
+    eu = rel_l2(ub.cpu().numpy(), ub_or)
+    es = rel_l2(s0b.cpu().numpy(), s0b_or)
+    print(f"C1 gradient err u {eu:.2e} s0 {es:.2e}")
+    assert eu <= GRAD_TOL and es <= GRAD_TOL
+
+
+@pytest.mark.parametrize("ns", [(64,), (16, 37, 64, 100)])
+def test_rope_batch_forward(ns):
+    insts = []
+    for j, n in enumerate(ns):
+        insts += W.small_rope_batch(2, n, 30, seed=200 + j)
+    sim, s0, u, traj, st = _run(insts)
+    assert (st == 0).all(), st
+    _check_states(sim, traj, insts)
+
+
+@pytest.mark.parametrize("dims", [((8, 8),), ((6, 5), (9, 7), (16, 16))])
+def test_cloth_batch_forward(dims):
+    insts = []
+    for j, (nx, ny) in enumerate(dims):
+        insts += W.small_cloth_batch(1, nx, ny, 20, seed=300 + j)
+    sim, s0, u, traj, st = _run(insts)
+    assert (st == 0).all(), st
+    _check_states(sim, traj, insts)
+
+
+def _backward_parity(insts, store="full", K=7):
+    import torch
+    from paper_2606_14188_amd import _lib as L
+    sim, s0, u, traj, st = _run(insts)
+    cots = [W.random_cotangent(i.n_s, 900 + j) for j, i in enumerate(insts)]
+    sT = sim.pack_states(cots)
+    s0b, ub = sim.backward(u, traj, sT_bar=sT)
+    torch.cuda.synchronize()
+    s0bp = sim.split(s0b, "s")
+    ubp = sim.split(ub, "u")
+    refs = [orollout(i)[0] for i in insts]
+    for j, inst in enumerate(insts):
+        s0r, ur = rollout_backward(inst, refs[j], sT_bar=cots[j])
+        eu, es = rel_l2(ubp[j], ur), rel_l2(s0bp[j], s0r)
+        print(f"instance {j} ({inst.kind} n={inst.n}): grad err u {eu:.2e} s0 {es:.2e}", flush=True)
+        assert eu <= GRAD_TOL and es <= GRAD_TOL
+    return sim, s0, u, traj, sT, s0b, ub
+
+
+def test_rope_backward():
+    insts = W.small_rope_batch(2, 64, 25, seed=401) + W.small_rope_batch(1, 23, 25, seed=402)
+    _backward_parity(insts)
+
+
+def test_cloth_backward():
+    insts = W.small_cloth_batch(1, 8, 8, 15, seed=411) + W.small_cloth_batch(1, 7, 5, 15, seed=412)
+    _backward_parity(insts)
+
+
+def test_checkpointed_backward_bitwise():
+    import torch
+    from paper_2606_14188_amd import _lib as L
+    insts = W.small_rope_batch(3, 40, 23, seed=421) + W.small_cloth_batch(1, 6, 6, 23, seed=422)
+    sim, s0, u, traj, st = _run(insts)
+    sT = sim.pack_states([W.random_cotangent(i.n_s, 950 + j) for j, i in enumerate(insts)])
+    s0b, ub = sim.backward(u, traj, sT_bar=sT)
+    for K in (1, 7, 23, 50):
+        ck = sim.rollout(s0, u, store=L.STORE_CKPT, ckpt_every=K)
+        s0k, ubk = sim.backward(u, ck, sT_bar=sT, store=L.STORE_CKPT, ckpt_every=K)
+        torch.cuda.synchronize()
+        assert torch.equal(s0k, s0b) and torch.equal(ubk, ub), K
+        # checkpoints are bitwise the stored states
+        full = sim.split(traj, "traj")
+        cks = sim.split(ck, "ckpt", K)
+        for j, inst in enumerate(insts):
+            tr = full[j].reshape(inst.T + 1, -1)
+            c = cks[j].reshape(-1, inst.n_s)
+            slots = list(range(0, inst.T, K)) + [inst.T]
+            assert np.array_equal(c, tr[slots])
+
+
+def test_determinism_and_mix_invariance():
+    import torch
+    insts = W.small_rope_batch(6, 64, 20, seed=431)
+    sim, s0, u, traj, st = _run(insts)
+    traj2 = sim.rollout(s0, u)
+    torch.cuda.synchronize()
+    assert torch.equal(traj, traj2)
+    alone, _, _, t1, _ = _run([insts[3]])
+    assert np.array_equal(sim.split(traj, "traj")[3], alone.split(t1, "traj")[0])
+
+
+def test_nonfinite_input_flags_only_that_instance():
+    insts = W.small_rope_batch(3, 20, 5, seed=441)
+    bad = insts[1].s0.copy()
+    bad[7] = np.nan
+    insts[1] = insts[1].replace(s0=bad)
+    sim, s0, u, traj, st = _run(insts)
+    assert st[1] == 4 and st[0] == 0 and st[2] == 0, st
+
+
+@pytest.mark.parametrize("kind", ["rope", "cloth"])
+def test_linearize_dense(kind):
+    import torch
+    if kind == "rope":
+        insts = W.small_rope_batch(1, 10, 4, seed=451) + W.small_rope_batch(1, 7, 4, seed=452)
+    else:
+        insts = W.small_cloth_batch(1, 4, 4, 3, seed=453)
+    sim, s0, u, traj, st = _run(insts)
+    A, Bm, _ = sim.linearize(traj, u)
+    torch.cuda.synchronize()
+    Ap, Bp = sim.split(A, "A"), sim.split(Bm, "B")
+    tp = sim.split(traj, "traj")
+    for j, inst in enumerate(insts):
+        ns, nu = inst.n_s, inst.n_u
+        Aj = Ap[j].reshape(inst.T, ns, ns)
+        Bj = Bp[j].reshape(inst.T, ns, nu)
+        tr = tp[j].reshape(inst.T + 1, ns).astype(np.float64)
+        for t in range(inst.T):
+            Ar, Br = StepDerivative(inst, tr[t], inst.u[t], inst.kappa_bwd).dense()
+            ea = np.linalg.norm(Aj[t] - Ar) / np.linalg.norm(Ar)
+            eb = np.linalg.norm(Bj[t] - Br) / np.linalg.norm(Br)
+            print(f"{kind} {j} t={t}: A err {ea:.2e} B err {eb:.2e}", flush=True)
+            assert ea <= JAC_TOL and eb <= JAC_TOL
+
+
+def test_jvp_tangents():
+    import torch
+    insts = W.small_cloth_batch(1, 6, 5, 4, seed=461) + W.small_rope_batch(1, 30, 4, seed=462)
+    sim, s0, u, traj, st = _run(insts)
+    k = 3
+    rng = np.random.default_rng(5)
+    ds = [rng.normal(size=(i.T, k, i.n_s)) for i in insts]
+    du = [rng.normal(size=(i.T, k, i.n_u)) for i in insts]
+    dst = sim.pack_states([d.ravel() for d in ds])
+    dut = sim.pack_states([d.ravel() for d in du])
+    _, _, out = sim.linearize(traj, u, dense=False, want_B=False, jvp_k=k, jvp_ds=dst, jvp_du=dut)
+    torch.cuda.synchronize()
+    h = out.cpu().numpy()
+    tp = sim.split(traj, "traj")
+    off = 0
+    for j, inst in enumerate(insts):
+        blk = h[off:off + inst.T * k * inst.n_s].reshape(inst.T, k, inst.n_s)
+        off += inst.T * k * inst.n_s
+        tr = tp[j].reshape(inst.T + 1, inst.n_s).astype(np.float64)
+        for t in range(inst.T):
+            d = StepDerivative(inst, tr[t], inst.u[t], inst.kappa_bwd)
+            n3 = 3 * inst.n
+            dxn, dvn = d.jvp(ds[j][t].T[:n3], ds[j][t].T[n3:], du[j][t].T)
+            ref = np.vstack([dxn, dvn]).T
+            e = rel_l2(blk[t], ref)
+            print(f"{inst.kind} t={t}: jvp err {e:.2e}", flush=True)
+            assert e <= JAC_TOL
+
+
+def test_autograd_function():
+    import torch
+    from paper_2606_14188_amd import rollout
+    insts = W.small_rope_batch(2, 32, 12, seed=471)
+    sim = _sim(insts)
+    s0 = sim.pack_states([i.s0 for i in insts]).requires_grad_(True)
+    u = sim.pack_controls([i.u for i in insts]).requires_grad_(True)
+    traj = rollout(sim, s0, u, mode="full")
+    w = torch.randn_like(traj)
+    (traj * w).sum().backward()
+    s0b, ub = sim.backward(u.detach(), traj.detach(), traj_bar=w)
+    torch.cuda.synchronize()
+    assert torch.equal(s0.grad, s0b) and torch.equal(u.grad, ub)
+    # final-state mode with checkpoints
+    s0.grad = None
+    u.grad = None
+    sT = rollout(sim, s0, u, mode="final", ckpt_every=5)
+    wT = torch.randn_like(sT)
+    (sT * wT).sum().backward()
+    full_sT = torch.cat([p[-6 * i.n:] for p, i in zip(torch.split(traj.detach(), [(i.T + 1) * i.n_s for i in insts]), insts)])
+    assert torch.equal(sT.detach(), full_sT)
+    s0b2, ub2 = sim.backward(u.detach(), traj.detach(), sT_bar=wT)
+    torch.cuda.synchronize()
+    assert torch.equal(s0.grad, s0b2) and torch.equal(u.grad, ub2)
+
+
+def test_c2_full_size_sampled():
+    """C2 at full size (1024 ropes of 64 nodes, 100 steps) in the launch the
+    benchmark times; four sampled instances against the oracle."""
+    insts = W.config_c2()
+    sim, s0, u, traj, st = _run(insts)
+    print("status counts", np.bincount(st, minlength=5))
+    assert (st == 0).all()
+    _check_states(sim, traj, insts, idx=[0, 341, 682, 1023])
+
+
+def test_c3_full_size_sampled():
+    """C3 at full size (256 cloths of 32x32, 60 steps); one sampled instance."""
+    insts = W.config_c3()
+    sim, s0, u, traj, st = _run(insts)
+    print("status counts", np.bincount(st, minlength=5))
+    assert (st == 0).all()
+    _check_states(sim, traj, insts, idx=[255])
+
+
+def test_c1_linearize_in_contact():
+    """Dense A_t/B_t along C1, where the rope lands on the ground and drapes
+    over the sphere: every step against the oracle at the same state."""
+    import torch
+    inst = W.config_c1()
+    sim, s0, u, traj, st = _run([inst])
+    A, Bm, _ = sim.linearize(traj, u)
+    torch.cuda.synchronize()
+    ns, nu, T = inst.n_s, inst.n_u, inst.T
+    Aj = A.cpu().numpy().reshape(T, ns, ns)
+    Bj = Bm.cpu().numpy().reshape(T, ns, nu)
+    tr = traj.cpu().numpy().reshape(T + 1, ns).astype(np.float64)
+    worst = 0.0
+    for t in range(T):
+        d = StepDerivative(inst, tr[t], inst.u[t], inst.kappa_bwd)
+        Ar, Br = d.dense()
+        ea = np.linalg.norm(Aj[t] - Ar) / np.linalg.norm(Ar)
+        eb = np.linalg.norm(Bj[t] - Br) / np.linalg.norm(Br)
+        print(f"C1 t={t}: A err {ea:.2e} B err {eb:.2e} max lam {d.res.lam.max():.2e} min gap {d.res.gap.min():.2e}",
+              flush=True)
+        worst = max(worst, ea, eb)
+    assert worst <= JAC_TOL
