@@ -90,7 +90,7 @@ def main():
     ap.add_argument("--no-linearize", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-workers", type=int, default=8)
     ap.add_argument("--cpu-per-worker", type=int, default=1)
-    ap.add_argument("--cpu-T", type=int, default=100)
+    ap.add_argument("--cpu-T", type=int, default=25)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); instances are independent "
