@@ -267,6 +267,51 @@ int cord_linearize(cord_sim* sim, const float* traj, const float* u, float* A, f
  */
 int cord_abi_sizes(int64_t* out, int32_t n);
 
+/* ---------------------------------------------------------------- launch */
+/*
+ * How cord_rollout and cord_rollout_backward are launched.  Instances are
+ * grouped into size classes (ropes with n <= 32, 64, 128, 256 nodes; cloths
+ * with n <= 64, 128, 256, 512, 1024 nodes); each class has one kernel
+ * configuration (threads per workgroup x particles per thread), chosen by
+ * default or by cord_autotune.  Results of an instance depend only on its
+ * class configuration, never on the rest of the batch or on the launch mode.
+ *   CORD_LAUNCH_GROUPED       one launch per class, one workgroup per instance
+ *   CORD_LAUNCH_PER_INSTANCE  one launch per instance (the plain launch)
+ *   CORD_LAUNCH_PERSISTENT    one persistent launch per class, each on its own
+ *                             stream forked from the caller's; workgroups pull
+ *                             instances (longest n*T first) from a device work
+ *                             queue until it is empty
+ *   CORD_LAUNCH_GRAPH         the persistent multi-stream sequence captured
+ *                             once into a hipGraph per set of buffers and then
+ *                             replayed with a single hipGraphLaunch
+ */
+#define CORD_LAUNCH_GROUPED       0
+#define CORD_LAUNCH_PER_INSTANCE  1
+#define CORD_LAUNCH_PERSISTENT    2
+#define CORD_LAUNCH_GRAPH         3
+
+/* Select the launch mode (default CORD_LAUNCH_GROUPED).  CORD_EINVAL for an
+ * unknown mode.  Changing the mode drops cached graphs. */
+int cord_sim_set_launch(cord_sim* sim, int32_t mode);
+
+/*
+ * Autotuner: for every size class, time each kernel configuration that covers
+ * the class (a forward rollout of up to `sample` instances of the class, with
+ * the caller's s0 and u, FINAL storage, median of 3 after a warm-up), keep
+ * the fastest and regroup.  cache_path (may be NULL) is a JSON file of
+ * previous choices, read first (classes found there are not re-timed) and
+ * rewritten afterwards.  Synchronises `stream`; allocates temporary device
+ * buffers.  Errors: CORD_EINVAL, CORD_ENOMEM, CORD_EHIP.
+ */
+int cord_autotune(cord_sim* sim, const float* s0, const float* u, int32_t sample, const char* cache_path,
+                  void* stream);
+
+/* Size classes in use: writes up to `cap` entries of topology (CORD_ROPE /
+ * CORD_CLOTH), largest node count of the class, threads per workgroup,
+ * particles per thread, and instance count; *count = number of classes. */
+int cord_sim_classes(const cord_sim* sim, int32_t* topo, int32_t* nmax, int32_t* nt, int32_t* ppt,
+                     int32_t* n_inst, int32_t cap, int32_t* count);
+
 /* Thread-local message of the last error on this thread ("" if none). */
 const char* cord_last_error(void);
 

@@ -26,6 +26,7 @@ ST_OK, ST_NEWTON_NOCONV, ST_NOT_PD, ST_QP_NOCONV, ST_NONFINITE = range(5)
 MAX_GRIP, MAX_SPHERE, MAX_BOX, MAX_OBST = 4, 4, 2, 4
 ROPE, CLOTH = 0, 1
 STORE_FULL, STORE_CKPT, STORE_FINAL = 0, 1, 2
+LAUNCH_GROUPED, LAUNCH_PER_INSTANCE, LAUNCH_PERSISTENT, LAUNCH_GRAPH = 0, 1, 2, 3
 
 
 class Params(ctypes.Structure):
@@ -75,6 +76,9 @@ _EXPORTS = {
     "cord_linearize": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(Jvp),
                                  c_void_p, c_void_p]),
     "cord_abi_sizes": (c_int32, [POINTER(c_int64), c_int32]),
+    "cord_sim_set_launch": (c_int32, [c_void_p, c_int32]),
+    "cord_autotune": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_char_p, c_void_p]),
+    "cord_sim_classes": (c_int32, [c_void_p] + [POINTER(c_int32)] * 5 + [c_int32, POINTER(c_int32)]),
     "cord_last_error": (c_char_p, []),
 }
 

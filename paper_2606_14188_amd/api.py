@@ -161,6 +161,25 @@ class Sim:
                                         _ptr(status), _stream()))
         return (A if dense else None), (Bm if want_B else None), out
 
+    # ------------------------------------------------------------ launch
+    def set_launch(self, mode: int):
+        """mode: _lib.LAUNCH_GROUPED / PER_INSTANCE / PERSISTENT / GRAPH."""
+        L.check(self.lib.cord_sim_set_launch(self._h, int(mode)))
+
+    def autotune(self, s0, u, sample: int = 64, cache_path=None):
+        path = cache_path.encode() if cache_path else None
+        L.check(self.lib.cord_autotune(self._h, _ptr(s0), _ptr(u), int(sample), path, _stream()))
+        return self.classes()
+
+    def classes(self):
+        """[(topology, nmax, threads, particles_per_thread, instances)] per size class."""
+        cap = 16
+        arrs = [(ctypes.c_int32 * cap)() for _ in range(5)]
+        cnt = ctypes.c_int32()
+        L.check(self.lib.cord_sim_classes(self._h, *[ctypes.cast(a, POINTER(ctypes.c_int32)) for a in arrs], cap,
+                                          byref(cnt)))
+        return [tuple(int(a[i]) for a in arrs) for i in range(cnt.value)]
+
     # ------------------------------------------------------------ helpers
     def pack_states(self, states):
         """list of per-instance numpy state vectors -> flat float32 tensor."""

@@ -4,6 +4,7 @@ Usage: python -m paper_2606_14188_amd.build [--verbose]
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -13,11 +14,13 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcord.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["cord_kernels.hip", "cord_api.cpp"]
+SOURCES = ["cord_kernels.hip", "cord_cfg_rope.hip", "cord_cfg_cloth_a.hip", "cord_cfg_cloth_b.hip",
+           "cord_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+BUILD_DIR = os.path.join(ROOT, "_build")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 math is kept off: its forms have given silent wrong results
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -25,18 +28,30 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *extra, *srcs, "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("libcord build failed")
+        raise RuntimeError("libcord build failed: " + " ".join(cmd[-3:]))
     if verbose and (r.stdout or r.stderr):
         sys.stderr.write(r.stdout + r.stderr)
+
+
+def build(verbose: bool = False, extra=(), jobs: int = 8) -> str:
+    """Compile every translation unit in parallel, then link libcord.so."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    objs = []
+    cmds = []
+    for src in SOURCES:
+        obj = os.path.join(BUILD_DIR, src + ".o")
+        objs.append(obj)
+        cmds.append([HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
+    with concurrent.futures.ThreadPoolExecutor(max_workers=max(1, min(jobs, len(cmds)))) as ex:
+        list(ex.map(lambda c: _run(c, verbose), cmds))
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

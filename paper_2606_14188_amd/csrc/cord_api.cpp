@@ -1,12 +1,17 @@
 // Host side of the libcord C ABI: validation, size classes, offsets,
-// workspaces and kernel launches.
+// workspaces, launch modes (grouped / per instance / persistent / hipGraph)
+// and the autotuner.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -34,36 +39,62 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
-#define CORD_HIP(call)                                                                  \
-    do {                                                                                \
-        hipError_t e_ = (call);                                                         \
+#define CORD_HIP(call)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
         if (e_ != hipSuccess) return fail(CORD_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+// size classes: upper node counts per topology
+const int kRopeBuckets[] = {32, 64, 128, 256};
+const int kClothBuckets[] = {64, 128, 256, 512, 1024};
+
+int bucket_of(int topo, int n) {
+    const int* b = topo == kRope ? kRopeBuckets : kClothBuckets;
+    const int nb = topo == kRope ? 4 : 5;
+    for (int i = 0; i < nb; ++i)
+        if (n <= b[i]) return b[i];
+    return -1;
+}
+
 struct Group {
+    int topo = 0;
+    int nmax = 0;              // bucket upper bound
     int cfg = -1;
-    std::vector<int32_t> ids;
+    std::vector<int32_t> ids;  // longest (n T) first
     int32_t* d_ids = nullptr;
     int tmax = 0;
+    int cap[2] = {1, 1};       // persistent grid: resident workgroups (rollout, backward)
 };
+
+enum Op { kOpRollout = 0, kOpBackward = 1 };
 
 }  // namespace
 
 struct cord_sim {
     int device = 0;
+    int n_cu = 1;
+    int launch = CORD_LAUNCH_GROUPED;
     std::vector<cord_instance_desc> desc;
     std::vector<InstDev> h;
     InstDev* d_inst = nullptr;
+    int32_t* d_ident = nullptr;      // 0..B-1 (per-instance launches)
     std::vector<Group> groups;
+    std::vector<int> group_of;       // instance -> group
     cord_sim_info_t info{};
     std::map<int, std::vector<int64_t>> ckpt_host;   // K -> offsets (n_inst + 1)
     std::map<int, int64_t*> ckpt_dev;
-    float* seg = nullptr;          // backward segment workspace
+    float* seg = nullptr;            // backward segment workspace
     size_t seg_floats = 0;
     int seg_K = 0;
     int64_t* seg_off = nullptr;
-    std::vector<int64_t> seg_off_host;
-    int32_t* scratch_status = nullptr;
+    int32_t* d_queues = nullptr;     // one work-queue counter per group
+    std::vector<hipStream_t> streams;
+    hipStream_t cap_stream = nullptr;   // graph capture (the caller's stream may be the null stream)
+    hipEvent_t fork_ev = nullptr;
+    std::vector<hipEvent_t> join_ev;
+    std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
+    std::vector<std::vector<uintptr_t>> graph_order;
 };
 
 namespace {
@@ -100,17 +131,45 @@ int validate(const cord_instance_desc& d, int i) {
     }
     const int nobs = (d.ground ? 1 : 0) + d.n_sphere + d.n_box;
     if (nobs > CORD_MAX_OBST) return fail(CORD_EUNSUPPORTED, "instance %d: %d obstacles > %d", i, nobs, CORD_MAX_OBST);
+    if (bucket_of(d.kind == CORD_ROPE ? kRope : kCloth, n) < 0)
+        return fail(CORD_EUNSUPPORTED, "instance %d: %d nodes exceed every kernel configuration", i, n);
     return CORD_OK;
 }
 
-int pick_config(const cord_instance_desc& d) {
+// first table entry of this topology covering nmax nodes
+int default_config(int topo, int nmax) {
     int count = 0;
     const KernelCfg* cfg = kernel_configs(&count);
-    const int n = d.nx * d.ny;
-    const int topo = d.kind == CORD_ROPE ? kRope : kCloth;
     for (int c = 0; c < count; ++c)
-        if (cfg[c].topo == topo && cfg[c].nt * cfg[c].ppt >= n) return c;
+        if (cfg[c].topo == topo && cfg[c].nt * cfg[c].ppt >= nmax) return c;
     return -1;
+}
+
+int find_config(int topo, int nt, int ppt) {
+    int count = 0;
+    const KernelCfg* cfg = kernel_configs(&count);
+    for (int c = 0; c < count; ++c)
+        if (cfg[c].topo == topo && cfg[c].nt == nt && cfg[c].ppt == ppt) return c;
+    return -1;
+}
+
+void drop_graphs(cord_sim* s) {
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    s->graphs.clear();
+    s->graph_order.clear();
+}
+
+int upload_group(cord_sim* s, Group& g) {
+    if (g.d_ids) { (void)hipFree(g.d_ids); g.d_ids = nullptr; }
+    CORD_HIP(hipMalloc(&g.d_ids, sizeof(int32_t) * g.ids.size()));
+    CORD_HIP(hipMemcpy(g.d_ids, g.ids.data(), sizeof(int32_t) * g.ids.size(), hipMemcpyHostToDevice));
+    int count = 0;
+    const KernelCfg* cfg = kernel_configs(&count);
+    for (int w = 0; w < 2; ++w) {
+        const int c = cfg[g.cfg].blocks_per_cu(w) * s->n_cu;
+        g.cap[w] = std::max(1, std::min((int)g.ids.size(), c));
+    }
+    return CORD_OK;
 }
 
 int ensure_ckpt(cord_sim* s, int K) {
@@ -134,15 +193,31 @@ int ensure_seg(cord_sim* s, int K) {
     const int B = (int)s->h.size();
     std::vector<int64_t> off(B + 1, 0);
     for (int b = 0; b < B; ++b) off[b + 1] = off[b] + (int64_t)K * s->h[b].n_s;
+    drop_graphs(s);
     if (s->seg) { (void)hipFree(s->seg); s->seg = nullptr; }
     if (s->seg_off) { (void)hipFree(s->seg_off); s->seg_off = nullptr; }
     if (hipMalloc(&s->seg, sizeof(float) * (size_t)off[B]) != hipSuccess)
         return fail(CORD_ENOMEM, "backward workspace of %lld floats", (long long)off[B]);
     CORD_HIP(hipMalloc(&s->seg_off, sizeof(int64_t) * B));
     CORD_HIP(hipMemcpy(s->seg_off, off.data(), sizeof(int64_t) * B, hipMemcpyHostToDevice));
-    s->seg_off_host = off;
     s->seg_floats = (size_t)off[B];
     s->seg_K = K;
+    return CORD_OK;
+}
+
+int ensure_streams(cord_sim* s) {
+    const size_t ng = s->groups.size();
+    if (!s->fork_ev) CORD_HIP(hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming));
+    if (!s->cap_stream) CORD_HIP(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    while (s->streams.size() < ng) {
+        hipStream_t st;
+        CORD_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));   // default priority
+        s->streams.push_back(st);
+        hipEvent_t ev;
+        CORD_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        s->join_ev.push_back(ev);
+    }
+    if (!s->d_queues) CORD_HIP(hipMalloc(&s->d_queues, sizeof(int32_t) * std::max<size_t>(ng, 1) + 64));
     return CORD_OK;
 }
 
@@ -151,6 +226,138 @@ KArgs base_args(const cord_sim* s) {
     std::memset(&a, 0, sizeof(a));
     a.inst = s->d_inst;
     return a;
+}
+
+hipError_t launch_op(const KernelCfg& c, int op, const KArgs& a, int nblk, hipStream_t st) {
+    return op == kOpRollout ? c.rollout(a, nblk, st) : c.backward(a, nblk, st);
+}
+
+// Enqueue the persistent multi-stream sequence on `st` (capturable: the
+// queue counters are cleared by a kernel, not a memset).
+int enqueue_persistent(cord_sim* s, int op, KArgs a, hipStream_t st) {
+    int count = 0;
+    const KernelCfg* cfg = kernel_configs(&count);
+    const int ng = (int)s->groups.size();
+    CORD_HIP(launch_fill_i32(s->d_queues, ng, 0, st));
+    CORD_HIP(hipEventRecord(s->fork_ev, st));
+    for (int g = 0; g < ng; ++g) {
+        Group& G = s->groups[g];
+        hipStream_t sg = s->streams[g];
+        CORD_HIP(hipStreamWaitEvent(sg, s->fork_ev, 0));
+        a.ids = G.d_ids;
+        a.n_ids = (int)G.ids.size();
+        a.queue = s->d_queues + g;
+        CORD_HIP(launch_op(cfg[G.cfg], op, a, G.cap[op], sg));
+        CORD_HIP(hipEventRecord(s->join_ev[g], sg));
+        CORD_HIP(hipStreamWaitEvent(st, s->join_ev[g], 0));
+    }
+    return CORD_OK;
+}
+
+std::vector<uintptr_t> graph_key(int op, const KArgs& a) {
+    return {(uintptr_t)op, (uintptr_t)a.s0, (uintptr_t)a.u, (uintptr_t)a.traj, (uintptr_t)a.final_out,
+            (uintptr_t)a.traj_in, (uintptr_t)a.traj_bar, (uintptr_t)a.sT_bar, (uintptr_t)a.s0_bar,
+            (uintptr_t)a.u_bar, (uintptr_t)a.status, (uintptr_t)a.counters, (uintptr_t)a.store,
+            (uintptr_t)a.ckpt_every, (uintptr_t)a.use_kappa_bwd, (uintptr_t)a.seg};
+}
+
+int launch_all(cord_sim* s, int op, KArgs a, hipStream_t st) {
+    int count = 0;
+    const KernelCfg* cfg = kernel_configs(&count);
+    switch (s->launch) {
+        case CORD_LAUNCH_PER_INSTANCE: {
+            for (int i = 0; i < (int)s->h.size(); ++i) {
+                a.ids = s->d_ident + i;
+                a.n_ids = 1;
+                a.queue = nullptr;
+                CORD_HIP(launch_op(cfg[s->groups[s->group_of[i]].cfg], op, a, 1, st));
+            }
+            return CORD_OK;
+        }
+        case CORD_LAUNCH_PERSISTENT: {
+            int rc = ensure_streams(s);
+            if (rc) return rc;
+            return enqueue_persistent(s, op, a, st);
+        }
+        case CORD_LAUNCH_GRAPH: {
+            int rc = ensure_streams(s);
+            if (rc) return rc;
+            auto key = graph_key(op, a);
+            auto it = s->graphs.find(key);
+            if (it == s->graphs.end()) {
+                hipGraph_t graph = nullptr;
+                hipStream_t cs = s->cap_stream;
+                CORD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+                rc = enqueue_persistent(s, op, a, cs);
+                hipError_t e = hipStreamEndCapture(cs, &graph);
+                if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+                if (e != hipSuccess) return fail(CORD_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+                hipGraphExec_t ex = nullptr;
+                e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) return fail(CORD_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+                if (s->graph_order.size() >= 16) {
+                    auto old = s->graph_order.front();
+                    s->graph_order.erase(s->graph_order.begin());
+                    (void)hipGraphExecDestroy(s->graphs[old]);
+                    s->graphs.erase(old);
+                }
+                it = s->graphs.emplace(key, ex).first;
+                s->graph_order.push_back(key);
+            }
+            CORD_HIP(hipGraphLaunch(it->second, st));
+            return CORD_OK;
+        }
+        default: {
+            for (const Group& G : s->groups) {
+                a.ids = G.d_ids;
+                a.n_ids = (int)G.ids.size();
+                a.queue = nullptr;
+                CORD_HIP(launch_op(cfg[G.cfg], op, a, a.n_ids, st));
+            }
+            return CORD_OK;
+        }
+    }
+}
+
+// ---- tiny JSON cache: {"entries": [[topo, nmax, nt, ppt], ...]}
+std::vector<std::vector<int>> read_cache(const char* path) {
+    std::vector<std::vector<int>> out;
+    if (!path) return out;
+    std::ifstream f(path);
+    if (!f) return out;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    std::string t = ss.str();
+    size_t p = t.find("\"entries\"");
+    if (p == std::string::npos) return out;
+    p = t.find('[', p);
+    if (p == std::string::npos) return out;
+    ++p;
+    while (true) {
+        size_t a = t.find('[', p), e = t.find(']', p);
+        if (a == std::string::npos || e == std::string::npos || e < a) break;
+        size_t b = t.find(']', a);
+        std::string inner = t.substr(a + 1, b - a - 1);
+        std::vector<int> v;
+        std::stringstream is(inner);
+        std::string tok;
+        while (std::getline(is, tok, ',')) v.push_back(std::atoi(tok.c_str()));
+        if (v.size() == 4) out.push_back(v);
+        p = b + 1;
+    }
+    return out;
+}
+
+bool write_cache(const char* path, const std::vector<std::vector<int>>& e) {
+    if (!path) return true;
+    std::ofstream f(path);
+    if (!f) return false;
+    f << "{\"format\": \"topo, nmax, threads, particles_per_thread\", \"entries\": [";
+    for (size_t i = 0; i < e.size(); ++i)
+        f << (i ? ", " : "") << "[" << e[i][0] << ", " << e[i][1] << ", " << e[i][2] << ", " << e[i][3] << "]";
+    f << "]}\n";
+    return (bool)f;
 }
 
 }  // namespace
@@ -178,11 +385,13 @@ int cord_sim_create(const cord_instance_desc* inst, int32_t n_inst, cord_sim** o
     cord_sim* s = new (std::nothrow) cord_sim();
     if (!s) return fail(CORD_ENOMEM, "host allocation");
     if (hipGetDevice(&s->device) != hipSuccess) { delete s; return fail(CORD_EHIP, "hipGetDevice failed"); }
+    if (hipDeviceGetAttribute(&s->n_cu, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess) s->n_cu = 1;
     s->desc.assign(inst, inst + n_inst);
     s->h.resize(n_inst);
+    s->group_of.assign(n_inst, -1);
     int64_t so = 0, uo = 0, to = 0, tns = 0, ao = 0, bo = 0;
     int max_n = 0, max_T = 0;
-    std::map<int, int> cfg_group;
+    std::map<std::pair<int, int>, int> class_group;
     for (int i = 0; i < n_inst; ++i) {
         const cord_instance_desc& d = inst[i];
         InstDev& I = s->h[i];
@@ -216,41 +425,62 @@ int cord_sim_create(const cord_instance_desc* inst, int32_t n_inst, cord_sim** o
         bo += (int64_t)I.T * I.n_s * I.n_u;
         max_n = I.n > max_n ? I.n : max_n;
         max_T = I.T > max_T ? I.T : max_T;
-        const int c = pick_config(d);
-        if (c < 0) { delete s; return fail(CORD_EUNSUPPORTED, "instance %d: %d nodes exceed every kernel configuration", i, I.n); }
-        if (!cfg_group.count(c)) { cfg_group[c] = (int)s->groups.size(); s->groups.push_back(Group{}); s->groups.back().cfg = c; }
-        Group& g = s->groups[cfg_group[c]];
-        g.ids.push_back(i);
-        g.tmax = I.T > g.tmax ? I.T : g.tmax;
+        const int bkt = bucket_of(I.kind, I.n);
+        auto key = std::make_pair((int)I.kind, bkt);
+        if (!class_group.count(key)) {
+            class_group[key] = (int)s->groups.size();
+            Group G;
+            G.topo = I.kind;
+            G.nmax = bkt;
+            G.cfg = default_config(I.kind, bkt);
+            s->groups.push_back(G);
+        }
+        const int gi = class_group[key];
+        s->groups[gi].ids.push_back(i);
+        s->groups[gi].tmax = std::max(s->groups[gi].tmax, I.T);
+        s->group_of[i] = gi;
     }
     s->info.n_inst = n_inst;
     s->info.s_floats = so; s->info.u_floats = uo; s->info.traj_floats = to;
     s->info.A_floats = ao; s->info.B_floats = bo;
     s->info.max_n = max_n; s->info.max_T = max_T;
-    auto cleanup = [&](int code, const char* what) {
+    auto cleanup = [&](int code, const std::string& what) {
         cord_sim_destroy(s);
-        return fail(code, "%s", what);
+        return fail(code, "%s", what.c_str());
     };
+    for (Group& G : s->groups)   // longest work first
+        std::stable_sort(G.ids.begin(), G.ids.end(), [&](int a, int b) {
+            return (int64_t)s->h[a].n * s->h[a].T > (int64_t)s->h[b].n * s->h[b].T;
+        });
     if (hipMalloc(&s->d_inst, sizeof(InstDev) * n_inst) != hipSuccess) return cleanup(CORD_ENOMEM, "device instance table");
     if (hipMemcpy(s->d_inst, s->h.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice) != hipSuccess)
         return cleanup(CORD_EHIP, "upload of instance table failed");
-    for (Group& g : s->groups) {
-        if (hipMalloc(&g.d_ids, sizeof(int32_t) * g.ids.size()) != hipSuccess) return cleanup(CORD_ENOMEM, "device id table");
-        if (hipMemcpy(g.d_ids, g.ids.data(), sizeof(int32_t) * g.ids.size(), hipMemcpyHostToDevice) != hipSuccess)
-            return cleanup(CORD_EHIP, "upload of id table failed");
-    }
+    std::vector<int32_t> ident(n_inst);
+    for (int i = 0; i < n_inst; ++i) ident[i] = i;
+    if (hipMalloc(&s->d_ident, sizeof(int32_t) * n_inst) != hipSuccess) return cleanup(CORD_ENOMEM, "device id table");
+    if (hipMemcpy(s->d_ident, ident.data(), sizeof(int32_t) * n_inst, hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(CORD_EHIP, "upload of id table failed");
+    for (Group& G : s->groups)
+        if (upload_group(s, G)) return cleanup(CORD_EHIP, g_err);
     *out = s;
     return CORD_OK;
 }
 
 int cord_sim_destroy(cord_sim* s) {
     if (!s) return CORD_OK;
+    drop_graphs(s);
     if (s->d_inst) (void)hipFree(s->d_inst);
+    if (s->d_ident) (void)hipFree(s->d_ident);
     for (Group& g : s->groups)
         if (g.d_ids) (void)hipFree(g.d_ids);
     for (auto& kv : s->ckpt_dev) (void)hipFree(kv.second);
     if (s->seg) (void)hipFree(s->seg);
     if (s->seg_off) (void)hipFree(s->seg_off);
+    if (s->d_queues) (void)hipFree(s->d_queues);
+    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    for (hipEvent_t ev : s->join_ev) (void)hipEventDestroy(ev);
+    if (s->fork_ev) (void)hipEventDestroy(s->fork_ev);
     delete s;
     return CORD_OK;
 }
@@ -283,6 +513,31 @@ int cord_sim_offsets(const cord_sim* s, int32_t K, int64_t* s_off, int64_t* u_of
     return CORD_OK;
 }
 
+int cord_sim_set_launch(cord_sim* s, int32_t mode) {
+    if (!s) return fail(CORD_EINVAL, "cord_sim_set_launch: NULL sim");
+    if (mode < CORD_LAUNCH_GROUPED || mode > CORD_LAUNCH_GRAPH) return fail(CORD_EINVAL, "unknown launch mode %d", mode);
+    if (mode != s->launch) drop_graphs(s);
+    s->launch = mode;
+    return CORD_OK;
+}
+
+int cord_sim_classes(const cord_sim* s, int32_t* topo, int32_t* nmax, int32_t* nt, int32_t* ppt, int32_t* n_inst,
+                     int32_t cap, int32_t* count) {
+    if (!s || !count) return fail(CORD_EINVAL, "cord_sim_classes: NULL argument");
+    int c = 0;
+    const KernelCfg* cfg = kernel_configs(&c);
+    *count = (int32_t)s->groups.size();
+    for (int g = 0; g < (int)s->groups.size() && g < cap; ++g) {
+        const Group& G = s->groups[g];
+        if (topo) topo[g] = G.topo == kRope ? CORD_ROPE : CORD_CLOTH;
+        if (nmax) nmax[g] = G.nmax;
+        if (nt) nt[g] = cfg[G.cfg].nt;
+        if (ppt) ppt[g] = cfg[G.cfg].ppt;
+        if (n_inst) n_inst[g] = (int32_t)G.ids.size();
+    }
+    return CORD_OK;
+}
+
 int cord_rollout(cord_sim* s, const float* s0, const float* u, float* traj, int32_t* inst_status,
                  const cord_rollout_opts* opts, void* stream) {
     g_err.clear();
@@ -305,15 +560,7 @@ int cord_rollout(cord_sim* s, const float* s0, const float* u, float* traj, int3
     }
     a.s0 = s0; a.u = u; a.traj = traj; a.status = inst_status; a.counters = o.counters;
     a.final_out = o.final_state;
-    int count = 0;
-    const KernelCfg* cfg = kernel_configs(&count);
-    hipStream_t st = (hipStream_t)stream;
-    for (const Group& g : s->groups) {
-        a.ids = g.d_ids;
-        a.n_ids = (int)g.ids.size();
-        CORD_HIP(cfg[g.cfg].rollout(a, a.n_ids, st));
-    }
-    return CORD_OK;
+    return launch_all(s, kOpRollout, a, (hipStream_t)stream);
 }
 
 int cord_rollout_backward(cord_sim* s, const float* u, const float* traj, const float* traj_bar, float* s0_bar,
@@ -342,15 +589,7 @@ int cord_rollout_backward(cord_sim* s, const float* u, const float* traj, const 
     }
     a.u = u; a.traj_in = traj; a.traj_bar = traj_bar; a.sT_bar = o.sT_bar;
     a.s0_bar = s0_bar; a.u_bar = u_bar; a.status = inst_status; a.counters = o.counters;
-    int count = 0;
-    const KernelCfg* cfg = kernel_configs(&count);
-    hipStream_t st = (hipStream_t)stream;
-    for (const Group& g : s->groups) {
-        a.ids = g.d_ids;
-        a.n_ids = (int)g.ids.size();
-        CORD_HIP(cfg[g.cfg].backward(a, a.n_ids, st));
-    }
-    return CORD_OK;
+    return launch_all(s, kOpBackward, a, (hipStream_t)stream);
 }
 
 int cord_linearize(cord_sim* s, const float* traj, const float* u, float* A, float* Bm, const cord_jvp* jvp,
@@ -372,6 +611,76 @@ int cord_linearize(cord_sim* s, const float* traj, const float* u, float* A, flo
         a.n_ids = (int)g.ids.size();
         CORD_HIP(cfg[g.cfg].linearize(a, a.n_ids, g.tmax, st));
     }
+    return CORD_OK;
+}
+
+int cord_autotune(cord_sim* s, const float* s0, const float* u, int32_t sample, const char* cache_path, void* stream) {
+    g_err.clear();
+    if (!s || !s0 || (!u && s->info.u_floats > 0) || sample < 1) return fail(CORD_EINVAL, "cord_autotune: bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    int count = 0;
+    const KernelCfg* cfg = kernel_configs(&count);
+    auto cache = read_cache(cache_path);
+    float* out = nullptr;
+    if (hipMalloc(&out, sizeof(float) * (size_t)s->info.s_floats) != hipSuccess) return fail(CORD_ENOMEM, "autotune buffer");
+    int32_t* ids = nullptr;
+    if (hipMalloc(&ids, sizeof(int32_t) * (size_t)sample) != hipSuccess) {
+        (void)hipFree(out);
+        return fail(CORD_ENOMEM, "autotune ids");
+    }
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    int rc = CORD_OK;
+    for (Group& G : s->groups) {
+        const int ctopo = G.topo == kRope ? CORD_ROPE : CORD_CLOTH;
+        int chosen = -1;
+        for (const auto& e : cache)
+            if (e[0] == ctopo && e[1] == G.nmax) chosen = find_config(G.topo, e[2], e[3]);
+        if (chosen < 0) {
+            // sample: the first `sample` ids (longest first) of the class
+            const int ns = std::min<int>(sample, (int)G.ids.size());
+            if (hipMemcpy(ids, G.ids.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice) != hipSuccess) {
+                rc = fail(CORD_EHIP, "autotune upload");
+                break;
+            }
+            float best = 1e30f;
+            for (int c = 0; c < count && !rc; ++c) {
+                if (cfg[c].topo != G.topo || cfg[c].nt * cfg[c].ppt < G.nmax) continue;
+                KArgs a = base_args(s);
+                a.store = CORD_STORE_FINAL;
+                a.ckpt_every = 1;
+                a.s0 = s0; a.u = u; a.traj = out;
+                a.ids = ids; a.n_ids = ns;
+                std::vector<float> t;
+                for (int r = 0; r < 4; ++r) {
+                    (void)hipEventRecord(e0, st);
+                    if (cfg[c].rollout(a, ns, st) != hipSuccess) { rc = fail(CORD_EHIP, "autotune launch"); break; }
+                    (void)hipEventRecord(e1, st);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    if (r) t.push_back(ms);
+                }
+                if (rc) break;
+                std::sort(t.begin(), t.end());
+                if (t[t.size() / 2] < best) { best = t[t.size() / 2]; chosen = c; }
+            }
+            if (rc) break;
+            cache.push_back({ctopo, G.nmax, cfg[chosen].nt, cfg[chosen].ppt});
+        }
+        if (chosen >= 0 && chosen != G.cfg) {
+            G.cfg = chosen;
+            if ((rc = upload_group(s, G))) break;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    (void)hipFree(ids);
+    drop_graphs(s);
+    if (rc) return rc;
+    if (!write_cache(cache_path, cache)) return fail(CORD_EINVAL, "cannot write autotune cache %s", cache_path);
     return CORD_OK;
 }
 

@@ -62,6 +62,7 @@ struct KArgs {
     float* jvp_out;
     int32_t* status;
     uint32_t* counters;
+    int32_t* queue;            // persistent launch: work-queue counter (zeroed before launch), or null
 };
 
 }  // namespace cord

@@ -16,6 +16,7 @@ struct KernelCfg {
     hipError_t (*rollout)(const KArgs&, int nblk, hipStream_t);
     hipError_t (*backward)(const KArgs&, int nblk, hipStream_t);
     hipError_t (*linearize)(const KArgs&, int nblk, int tmax, hipStream_t);
+    int (*blocks_per_cu)(int which);   // occupancy of the rollout (0) / backward (1) kernel
 };
 
 const KernelCfg* kernel_configs(int* count);

@@ -1,288 +1,29 @@
-// Rollout, adjoint and linearization kernels, one workgroup per instance
-// (linearize: per instance and step), instantiated per size class.
+// Configuration table over all size-class translation units, and the
+// small utility kernels.
 #include <hip/hip_runtime.h>
 
-#include "../../include/cord.h"
-#include "cord_internal.h"
+#include <vector>
+
 #include "cord_kernels.h"
-#include "cord_solver.h"
 
 namespace cord {
 
-template <int TOPO, int NT, int PPT, int NOBS>
-__global__ __launch_bounds__(NT) void rollout_kernel(KArgs a) {
-    extern __shared__ float lds[];
-    const int id = a.ids[blockIdx.x];
-    const InstDev& I = a.inst[id];
-    Solver<TOPO, NT, PPT, NOBS> S;
-    S.init(I, lds);
-    S.load_state(a.s0 + I.s_off);
-    const float kappa = a.use_kappa_bwd ? I.kappa_bwd : I.kappa_fwd;
-    const int T = I.T, ns = I.n_s, K = a.ckpt_every;
-    if (a.store == CORD_STORE_FULL) S.store_state(a.traj + I.traj_off);
-    else if (a.store == CORD_STORE_CKPT) S.store_state(a.traj + a.ckpt_off[id]);
-    for (int t = 0; t < T; ++t) {
-        S.solve_step(a.u + I.u_off + (int64_t)t * I.n_u, kappa);
-        S.advance();
-        if (a.store == CORD_STORE_FULL) {
-            S.store_state(a.traj + I.traj_off + (int64_t)(t + 1) * ns);
-        } else if (a.store == CORD_STORE_CKPT) {
-            if ((t + 1) % K == 0 || t + 1 == T)
-                S.store_state(a.traj + a.ckpt_off[id] + (int64_t)((t + K) / K) * ns);
-        } else if (t + 1 == T) {
-            S.store_state(a.traj + I.s_off);
-        }
-    }
-    if (a.final_out) S.store_state(a.final_out + I.s_off);
-    if (threadIdx.x == 0) {
-        if (a.status) a.status[id] = S.status;
-        if (a.counters)
-            for (int i = 0; i < 4; ++i) a.counters[4 * id + i] += S.cnt[i];
-    }
-}
-
-template <int PPT>
-__device__ __forceinline__ void add_cot(float xb[PPT][3], float vb[PPT][3], const float* s, int n, int NT) {
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int p = (int)threadIdx.x + k * NT;
-        if (p < n) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) { xb[k][c] += s[3 * p + c]; vb[k][c] += s[3 * n + 3 * p + c]; }
-        }
-    }
-}
-
-// Re-solve step t at kappa_bwd from the loaded state, apply its VJP, write
-// u_bar[t] and add the state cotangent of traj_bar[t].
-template <int TOPO, int NT, int PPT, int NOBS>
-__device__ __forceinline__ void adjoint_step(Solver<TOPO, NT, PPT, NOBS>& S, const KArgs& a, const InstDev& I, int t,
-                                             float xb[PPT][3], float vb[PPT][3], float ub[PPT][3]) {
-    const int nu = I.n_u;
-    S.solve_step(a.u + I.u_off + (int64_t)t * nu, I.kappa_bwd);
-    float dxb[PPT][3];
-    S.adjoint(xb, vb, ub, I.kappa_bwd, dxb);
-#pragma unroll
-    for (int k = 0; k < PPT; ++k)
-        if (S.active(k) && !S.isfree(k)) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) a.u_bar[I.u_off + (int64_t)t * nu + 3 * S.grip[k] + c] = ub[k][c];
-        }
-    if (a.traj_bar) add_cot<PPT>(xb, vb, a.traj_bar + I.traj_off + (int64_t)t * I.n_s, I.n, NT);
-}
-
-template <int TOPO, int NT, int PPT, int NOBS>
-__global__ __launch_bounds__(NT) void backward_kernel(KArgs a) {
-    extern __shared__ float lds[];
-    const int id = a.ids[blockIdx.x];
-    const InstDev& I = a.inst[id];
-    Solver<TOPO, NT, PPT, NOBS> S;
-    S.init(I, lds);
-    const int T = I.T, ns = I.n_s, nu = I.n_u, n = I.n, K = a.ckpt_every;
-    const float kf = a.use_kappa_bwd ? I.kappa_bwd : I.kappa_fwd;
-    float xb[PPT][3], vb[PPT][3], ub[PPT][3];
-#pragma unroll
-    for (int k = 0; k < PPT; ++k)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) { xb[k][c] = 0.f; vb[k][c] = 0.f; }
-    if (a.traj_bar) add_cot<PPT>(xb, vb, a.traj_bar + I.traj_off + (int64_t)T * ns, n, NT);
-    else if (a.sT_bar) add_cot<PPT>(xb, vb, a.sT_bar + I.s_off, n, NT);
-
-    if (a.store == CORD_STORE_FULL) {
-        for (int t = T - 1; t >= 0; --t) {
-            S.load_state(a.traj_in + I.traj_off + (int64_t)t * ns);
-            adjoint_step<TOPO, NT, PPT, NOBS>(S, a, I, t, xb, vb, ub);
-        }
-    } else {
-        float* ws = a.seg + a.seg_off[id];
-        const int nseg = (T + K - 1) / K;
-        for (int sg = nseg - 1; sg >= 0; --sg) {
-            const int t0 = sg * K, t1 = min(T, t0 + K);
-            // recompute the segment's states with the forward configuration
-            S.load_state(a.traj_in + a.ckpt_off[id] + (int64_t)sg * ns);
-            S.store_state(ws);
-            for (int t = t0; t < t1 - 1; ++t) {
-                S.solve_step(a.u + I.u_off + (int64_t)t * nu, kf);
-                S.advance();
-                S.store_state(ws + (int64_t)(t + 1 - t0) * ns);
-            }
-            for (int t = t1 - 1; t >= t0; --t) {
-                S.load_state(ws + (int64_t)(t - t0) * ns);
-                adjoint_step<TOPO, NT, PPT, NOBS>(S, a, I, t, xb, vb, ub);
-            }
-        }
-    }
-    // s0_bar
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int p = (int)threadIdx.x + k * NT;
-        if (p < n) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                a.s0_bar[I.s_off + 3 * p + c] = xb[k][c];
-                a.s0_bar[I.s_off + 3 * n + 3 * p + c] = vb[k][c];
-            }
-        }
-    }
-    if (threadIdx.x == 0) {
-        if (a.status) a.status[id] = S.status;
-        if (a.counters)
-            for (int i = 0; i < 4; ++i) a.counters[4 * id + i] += S.cnt[i];
-    }
-}
-
-// One workgroup per (instance, step).  Dense rows of A_t/B_t come from one
-// VJP per free DoF row (rows written coalesced); JVP tangents from the
-// forward tangent map.
-template <int TOPO, int NT, int PPT, int NOBS>
-__global__ __launch_bounds__(NT) void linearize_kernel(KArgs a) {
-    extern __shared__ float lds[];
-    const int id = a.ids[blockIdx.x];
-    const InstDev& I = a.inst[id];
-    const int t = blockIdx.y;
-    if (t >= I.T) return;
-    Solver<TOPO, NT, PPT, NOBS> S;
-    S.init(I, lds);
-    const int n = I.n, ns = I.n_s, nu = I.n_u;
-    const float kb = I.kappa_bwd, dt = I.dt, idt = 1.0f / I.dt;
-    S.load_state(a.traj_in + I.traj_off + (int64_t)t * ns);
-    S.solve_step(a.u + I.u_off + (int64_t)t * nu, kb);
-
-    if (a.A || a.Bm) {
-        float* A = a.A ? a.A + I.A_off + (int64_t)t * ns * ns : nullptr;
-        float* Bm = a.Bm ? a.Bm + I.B_off + (int64_t)t * ns * nu : nullptr;
-        float xb[PPT][3], vb[PPT][3], ub[PPT][3];
-        for (int r = 0; r < 3 * n; ++r) {
-            const int pr = r / 3, cr = r - 3 * pr;
-            int gr = -1;
-            for (int j = 0; j < I.n_grip; ++j)
-                if (I.grip_node[j] == pr) gr = j;
-            float* Ax = A ? A + (int64_t)r * ns : nullptr;
-            float* Av = A ? A + (int64_t)(3 * n + r) * ns : nullptr;
-            if (gr >= 0) {
-                // x+_j = x_j + dt u_g ; v+_j = u_g
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    const int p = (int)threadIdx.x + k * NT;
-                    if (p >= n || !A) continue;
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        Ax[3 * p + c] = (p == pr && c == cr) ? 1.f : 0.f;
-                        Ax[3 * n + 3 * p + c] = 0.f;
-                        Av[3 * p + c] = 0.f;
-                        Av[3 * n + 3 * p + c] = 0.f;
-                    }
-                }
-                if (Bm && (int)threadIdx.x < nu) {
-                    const int col = threadIdx.x;
-                    Bm[(int64_t)r * nu + col] = (col == 3 * gr + cr) ? dt : 0.f;
-                    Bm[(int64_t)(3 * n + r) * nu + col] = (col == 3 * gr + cr) ? 1.f : 0.f;
-                }
-                continue;
-            }
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                const int p = (int)threadIdx.x + k * NT;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) { xb[k][c] = (p == pr && c == cr) ? 1.f : 0.f; vb[k][c] = 0.f; }
-            }
-            float dxb[PPT][3];
-            S.adjoint(xb, vb, ub, kb, dxb);
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                const int p = (int)threadIdx.x + k * NT;
-                if (p >= n) continue;
-                if (A) {
-                    // row r of dv+/dx is (row r of dx+/dx - e_r)/dt = dxb/dt
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        Ax[3 * p + c] = xb[k][c];
-                        Ax[3 * n + 3 * p + c] = vb[k][c];
-                        Av[3 * p + c] = dxb[k][c] * idt;
-                        Av[3 * n + 3 * p + c] = vb[k][c] * idt;
-                    }
-                }
-                if (Bm && S.active(k) && !S.isfree(k)) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        Bm[(int64_t)r * nu + 3 * S.grip[k] + c] = ub[k][c];
-                        Bm[(int64_t)(3 * n + r) * nu + 3 * S.grip[k] + c] = ub[k][c] * idt;
-                    }
-                }
-            }
-        }
-    }
-
-    if (a.jvp_out) {
-        const int kt = a.jvp_k;
-        float dx[PPT][3], dv[PPT][3], du[PPT][3], ox[PPT][3], ov[PPT][3];
-        for (int i = 0; i < kt; ++i) {
-            const int64_t sbase = (int64_t)kt * I.tns_off + ((int64_t)t * kt + i) * ns;
-            const int64_t ubase = (int64_t)kt * I.u_off + ((int64_t)t * kt + i) * nu;
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                const int p = (int)threadIdx.x + k * NT;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    dx[k][c] = (a.jvp_ds && p < n) ? a.jvp_ds[sbase + 3 * p + c] : 0.f;
-                    dv[k][c] = (a.jvp_ds && p < n) ? a.jvp_ds[sbase + 3 * n + 3 * p + c] : 0.f;
-                    du[k][c] = (a.jvp_du && S.active(k) && !S.isfree(k)) ? a.jvp_du[ubase + 3 * S.grip[k] + c] : 0.f;
-                }
-            }
-            S.tangent(dx, dv, du, ox, ov, kb);
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                const int p = (int)threadIdx.x + k * NT;
-                if (p >= n) continue;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    a.jvp_out[sbase + 3 * p + c] = ox[k][c];
-                    a.jvp_out[sbase + 3 * n + 3 * p + c] = ov[k][c];
-                }
-            }
-        }
-    }
-    if (threadIdx.x == 0 && a.status) atomicMax(&a.status[id], S.status);
-    if (threadIdx.x == 0 && a.counters)
-        for (int i = 0; i < 4; ++i) atomicAdd(&a.counters[4 * id + i], S.cnt[i]);
-}
-
-// ----------------------------------------------------------------- launch table
-template <int TOPO, int NT, int PPT, int NOBS>
-struct Launch {
-    static constexpr size_t kLds = sizeof(float) * lds_floats<NT, PPT>();
-    static hipError_t rollout(const KArgs& a, int nblk, hipStream_t s) {
-        hipLaunchKernelGGL((rollout_kernel<TOPO, NT, PPT, NOBS>), dim3(nblk), dim3(NT), kLds, s, a);
-        return hipGetLastError();
-    }
-    static hipError_t backward(const KArgs& a, int nblk, hipStream_t s) {
-        hipLaunchKernelGGL((backward_kernel<TOPO, NT, PPT, NOBS>), dim3(nblk), dim3(NT), kLds, s, a);
-        return hipGetLastError();
-    }
-    static hipError_t linearize(const KArgs& a, int nblk, int tmax, hipStream_t s) {
-        hipLaunchKernelGGL((linearize_kernel<TOPO, NT, PPT, NOBS>), dim3(nblk, tmax), dim3(NT), kLds, s, a);
-        return hipGetLastError();
-    }
-};
-
-#define CORD_CFG(TOPO, NT, PPT, NOBS) \
-    {TOPO, NT, PPT, NOBS, Launch<TOPO, NT, PPT, NOBS>::kLds, &Launch<TOPO, NT, PPT, NOBS>::rollout, \
-     &Launch<TOPO, NT, PPT, NOBS>::backward, &Launch<TOPO, NT, PPT, NOBS>::linearize}
-
-static const KernelCfg kConfigs[] = {
-    CORD_CFG(kRope, 64, 1, 4),
-    CORD_CFG(kRope, 128, 1, 4),
-    CORD_CFG(kRope, 256, 1, 4),
-    CORD_CFG(kCloth, 64, 1, 4),
-    CORD_CFG(kCloth, 128, 1, 4),
-    CORD_CFG(kCloth, 256, 1, 4),
-    CORD_CFG(kCloth, 512, 1, 4),
-    CORD_CFG(kCloth, 1024, 1, 4),
-};
+const KernelCfg* rope_configs(int* count);
+const KernelCfg* cloth_configs_a(int* count);
+const KernelCfg* cloth_configs_b(int* count);
 
 const KernelCfg* kernel_configs(int* count) {
-    *count = (int)(sizeof(kConfigs) / sizeof(kConfigs[0]));
-    return kConfigs;
+    static const std::vector<KernelCfg> all = [] {
+        std::vector<KernelCfg> v;
+        for (auto f : {rope_configs, cloth_configs_a, cloth_configs_b}) {
+            int c = 0;
+            const KernelCfg* t = f(&c);
+            v.insert(v.end(), t, t + c);
+        }
+        return v;
+    }();
+    *count = (int)all.size();
+    return all.data();
 }
 
 }  // namespace cord
