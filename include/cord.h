@@ -312,6 +312,99 @@ int cord_autotune(cord_sim* sim, const float* s0, const float* u, int32_t sample
 int cord_sim_classes(const cord_sim* sim, int32_t* topo, int32_t* nmax, int32_t* nt, int32_t* ppt,
                      int32_t* n_inst, int32_t cap, int32_t* count);
 
+/* ---------------------------------------------------------------- planning service */
+/*
+ * Gradient-based trajectory planning (the nominal (z, v) of Sec. 4.2, stage
+ * (1); "gradient-based trajectory optimization", Sec. 1 and Table 1), served
+ * with continuous batching.
+ *
+ * One request plans for one rope or cloth: n_cand candidate control
+ * sequences over the instance's horizon T are improved together by
+ * `iters` projected-gradient steps
+ *     u <- clip(u - step * dJ/du, -u_max, u_max),
+ *     J(u) = |x_T[goal_node] - goal|^2 + u_reg * sum_t |u_t|^2,
+ * each step being a batched forward rollout and adjoint of all candidates
+ * (cord_rollout / cord_rollout_backward).  Candidate 0 starts from u_warm,
+ * candidate c > 0 from u_warm + sigma * N(0, 1) (SplitMix64 + Box-Muller from
+ * `seed`) unless u_init gives all starts explicitly.  After the last step the
+ * candidates are rolled out once more, the lowest J wins (ties: lowest
+ * index), and for want_AB the dense A_t, B_t along the winner are computed
+ * (cord_linearize).  All of this runs on the device without host round trips;
+ * the winner's controls, trajectory and Jacobians stay on the device until the
+ * request completes, then are copied to host buffers owned by the server.
+ */
+typedef struct {
+    cord_instance_desc inst;   /* the object, its parameters and horizon T             */
+    const float* s0;           /* HOST [n_s] initial state                             */
+    const float* u_warm;       /* HOST [T][n_u] warm start, or NULL (zeros)            */
+    const float* u_init;       /* HOST [n_cand][T][n_u] explicit starts, or NULL       */
+    int32_t goal_node;         /* node whose final position is steered                 */
+    float goal[3];
+    uint64_t seed;
+    int32_t n_cand;            /* candidates, >= 1                                     */
+    int32_t iters;             /* gradient steps, >= 0                                 */
+    float step;                /* step size                                            */
+    float u_max;               /* |u| bound per component, > 0                         */
+    float sigma;               /* std of the candidate perturbation                    */
+    float u_reg;               /* control regularisation weight, >= 0                  */
+    int32_t want_AB;           /* nonzero: dense A_t, B_t along the winner             */
+    int32_t reserved;
+} cord_plan_request;
+
+typedef struct {
+    int32_t status;            /* CORD_OK, or the error code of a failed request       */
+    int32_t sim_status;        /* worst per-candidate solver status (CORD_ST_*)        */
+    int32_t best;              /* winning candidate                                    */
+    int32_t T, n_s, n_u, n_cand;
+    float cost;                /* J of the winner                                      */
+    const float* u;            /* HOST [T][n_u] winner controls                        */
+    const float* traj;         /* HOST [T+1][n_s] winner trajectory                    */
+    const float* A;            /* HOST [T][n_s][n_s] or NULL                           */
+    const float* B;            /* HOST [T][n_s][n_u] or NULL                           */
+    const float* costs;        /* HOST [n_cand] final J of every candidate             */
+    double t_submit, t_admit, t_done;   /* seconds on the server's steady clock        */
+} cord_plan_result;
+
+typedef struct cord_server cord_server;
+
+/*
+ * Start a planning server on `device`: one scheduler thread and `max_slots`
+ * device streams.  Requests are admitted in arrival order (a request that
+ * does not fit may be overtaken by at most 8 later ones) when a slot is free
+ * and its device footprint fits in what remains of `hbm_budget` bytes;
+ * admitted requests run concurrently, one per slot stream.  max_slots = 1 is
+ * the one-request-at-a-time server.  Errors: CORD_EINVAL, CORD_EHIP, CORD_ENOMEM.
+ */
+int cord_server_create(int32_t device, size_t hbm_budget, int32_t max_slots, int32_t queue_cap,
+                       cord_server** out);
+
+/* Stop accepting, finish or cancel queued work, join the thread, free all
+ * memory (including unreleased results). */
+int cord_server_destroy(cord_server* srv);
+
+/*
+ * Submit a request (copied; host pointers may be reused on return).  Never
+ * blocks.  Errors: CORD_EINVAL (bad request), CORD_EUNSUPPORTED (as
+ * cord_sim_create), CORD_EAGAIN (queue full), CORD_ETOOBIG (footprint above
+ * the whole budget).  *ticket identifies the request.
+ */
+int cord_plan_submit(cord_server* srv, const cord_plan_request* req, uint64_t* ticket);
+
+/* CORD_OK and *out filled if the request is done (its status field tells
+ * success), CORD_EAGAIN if still queued or running, CORD_EINVAL for an
+ * unknown ticket. */
+int cord_plan_poll(cord_server* srv, uint64_t ticket, cord_plan_result* out);
+
+/* As cord_plan_poll but waits up to timeout_ms (< 0: forever). */
+int cord_plan_wait(cord_server* srv, uint64_t ticket, int32_t timeout_ms, cord_plan_result* out);
+
+/* Free a finished request's result buffers; the ticket becomes unknown. */
+int cord_plan_release(cord_server* srv, uint64_t ticket);
+
+/* Server counters: submitted, admitted, completed, failed, queued now,
+ * running now, peak queue depth, bytes in use (host array of 8 int64). */
+int cord_server_stats(cord_server* srv, int64_t* out8);
+
 /* Thread-local message of the last error on this thread ("" if none). */
 const char* cord_last_error(void);
 

@@ -62,6 +62,21 @@ class Jvp(ctypes.Structure):
     _fields_ = [("k", c_int32), ("ds", c_void_p), ("du", c_void_p), ("out", c_void_p)]
 
 
+class PlanRequest(ctypes.Structure):
+    _fields_ = [("inst", InstanceDesc), ("s0", c_void_p), ("u_warm", c_void_p), ("u_init", c_void_p),
+                ("goal_node", c_int32), ("goal", c_float * 3), ("seed", ctypes.c_uint64), ("n_cand", c_int32),
+                ("iters", c_int32), ("step", c_float), ("u_max", c_float), ("sigma", c_float), ("u_reg", c_float),
+                ("want_AB", c_int32), ("reserved", c_int32)]
+
+
+class PlanResult(ctypes.Structure):
+    _fields_ = [("status", c_int32), ("sim_status", c_int32), ("best", c_int32), ("T", c_int32), ("n_s", c_int32),
+                ("n_u", c_int32), ("n_cand", c_int32), ("cost", c_float), ("u", POINTER(c_float)),
+                ("traj", POINTER(c_float)), ("A", POINTER(c_float)), ("B", POINTER(c_float)),
+                ("costs", POINTER(c_float)), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
 _STRUCTS = [Params, InstanceDesc, SimInfo, RolloutOpts, BackwardOpts, Jvp]
 
 _EXPORTS = {
@@ -80,6 +95,13 @@ _EXPORTS = {
     "cord_autotune": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_char_p, c_void_p]),
     "cord_sim_classes": (c_int32, [c_void_p] + [POINTER(c_int32)] * 5 + [c_int32, POINTER(c_int32)]),
     "cord_last_error": (c_char_p, []),
+    "cord_server_create": (c_int32, [c_int32, ctypes.c_size_t, c_int32, c_int32, POINTER(c_void_p)]),
+    "cord_server_destroy": (c_int32, [c_void_p]),
+    "cord_plan_submit": (c_int32, [c_void_p, POINTER(PlanRequest), POINTER(ctypes.c_uint64)]),
+    "cord_plan_poll": (c_int32, [c_void_p, ctypes.c_uint64, POINTER(PlanResult)]),
+    "cord_plan_wait": (c_int32, [c_void_p, ctypes.c_uint64, c_int32, POINTER(PlanResult)]),
+    "cord_plan_release": (c_int32, [c_void_p, ctypes.c_uint64]),
+    "cord_server_stats": (c_int32, [c_void_p, POINTER(c_int64)]),
 }
 
 _lib = None

@@ -45,6 +45,9 @@ int fail(int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(CORD_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+}  // namespace
+
+namespace cord {
 // size classes: upper node counts per topology
 const int kRopeBuckets[] = {32, 64, 128, 256};
 const int kClothBuckets[] = {64, 128, 256, 512, 1024};
@@ -56,6 +59,9 @@ int bucket_of(int topo, int n) {
         if (n <= b[i]) return b[i];
     return -1;
 }
+}  // namespace cord
+
+namespace {
 
 struct Group {
     int topo = 0;
@@ -97,7 +103,7 @@ struct cord_sim {
     std::vector<std::vector<uintptr_t>> graph_order;
 };
 
-namespace {
+namespace cord {
 
 int validate(const cord_instance_desc& d, int i) {
     const cord_params& p = d.params;
@@ -136,6 +142,31 @@ int validate(const cord_instance_desc& d, int i) {
     return CORD_OK;
 }
 
+// Device descriptor of one instance (offsets are set by the caller).
+void fill_instdev(const cord_instance_desc& d, InstDev& I) {
+    std::memset(&I, 0, sizeof(I));
+    I.kind = d.kind == CORD_ROPE ? kRope : kCloth;
+    I.nx = d.nx; I.ny = d.ny; I.n = d.nx * d.ny;
+    I.T = d.T; I.n_grip = d.n_grip;
+    I.n_s = 6 * I.n; I.n_u = 3 * d.n_grip;
+    for (int g = 0; g < d.n_grip; ++g) I.grip_node[g] = d.grip_node[g];
+    int o = 0;
+    if (d.ground) { I.obs_type[o] = kObsGround; ++o; }
+    for (int k = 0; k < d.n_sphere; ++k, ++o) {
+        I.obs_type[o] = kObsSphere;
+        for (int c = 0; c < 4; ++c) I.obs[o][c] = d.sphere[k][c];
+    }
+    for (int k = 0; k < d.n_box; ++k, ++o) {
+        I.obs_type[o] = kObsBox;
+        for (int c = 0; c < 7; ++c) I.obs[o][c] = d.box[k][c];
+    }
+    I.n_obs = o;
+    I.h = d.h; I.mass = d.mass; I.k_struct = d.k_struct; I.k_shear = d.k_shear; I.k_bend = d.k_bend;
+    I.dt = d.params.dt; I.gamma = d.params.gamma;
+    I.kappa_fwd = d.params.kappa_fwd; I.kappa_bwd = d.params.kappa_bwd;
+    I.g0 = d.params.gravity[0]; I.g1 = d.params.gravity[1]; I.g2 = d.params.gravity[2];
+}
+
 // first table entry of this topology covering nmax nodes
 int default_config(int topo, int nmax) {
     int count = 0;
@@ -152,6 +183,12 @@ int find_config(int topo, int nt, int ppt) {
         if (cfg[c].topo == topo && cfg[c].nt == nt && cfg[c].ppt == ppt) return c;
     return -1;
 }
+
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+}  // namespace cord
+
+namespace {
 
 void drop_graphs(cord_sim* s) {
     for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -395,27 +432,7 @@ int cord_sim_create(const cord_instance_desc* inst, int32_t n_inst, cord_sim** o
     for (int i = 0; i < n_inst; ++i) {
         const cord_instance_desc& d = inst[i];
         InstDev& I = s->h[i];
-        std::memset(&I, 0, sizeof(I));
-        I.kind = d.kind == CORD_ROPE ? kRope : kCloth;
-        I.nx = d.nx; I.ny = d.ny; I.n = d.nx * d.ny;
-        I.T = d.T; I.n_grip = d.n_grip;
-        I.n_s = 6 * I.n; I.n_u = 3 * d.n_grip;
-        for (int g = 0; g < d.n_grip; ++g) I.grip_node[g] = d.grip_node[g];
-        int o = 0;
-        if (d.ground) { I.obs_type[o] = kObsGround; ++o; }
-        for (int k = 0; k < d.n_sphere; ++k, ++o) {
-            I.obs_type[o] = kObsSphere;
-            for (int c = 0; c < 4; ++c) I.obs[o][c] = d.sphere[k][c];
-        }
-        for (int k = 0; k < d.n_box; ++k, ++o) {
-            I.obs_type[o] = kObsBox;
-            for (int c = 0; c < 7; ++c) I.obs[o][c] = d.box[k][c];
-        }
-        I.n_obs = o;
-        I.h = d.h; I.mass = d.mass; I.k_struct = d.k_struct; I.k_shear = d.k_shear; I.k_bend = d.k_bend;
-        I.dt = d.params.dt; I.gamma = d.params.gamma;
-        I.kappa_fwd = d.params.kappa_fwd; I.kappa_bwd = d.params.kappa_bwd;
-        I.g0 = d.params.gravity[0]; I.g1 = d.params.gravity[1]; I.g2 = d.params.gravity[2];
+        fill_instdev(d, I);
         I.s_off = so; I.u_off = uo; I.traj_off = to; I.tns_off = tns; I.A_off = ao; I.B_off = bo;
         so += I.n_s;
         uo += (int64_t)I.T * I.n_u;

@@ -1,0 +1,13 @@
+// Host-side helpers shared by the simulator API and the planning server.
+#pragma once
+#include "../../include/cord.h"
+#include "cord_internal.h"
+
+namespace cord {
+int validate(const cord_instance_desc& d, int i);
+void fill_instdev(const cord_instance_desc& d, InstDev& I);
+int bucket_of(int topo, int n);
+int default_config(int topo, int nmax);
+int set_error(int code, const char* msg);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+}  // namespace cord

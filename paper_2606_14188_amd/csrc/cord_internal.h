@@ -63,6 +63,7 @@ struct KArgs {
     int32_t* status;
     uint32_t* counters;
     int32_t* queue;            // persistent launch: work-queue counter (zeroed before launch), or null
+    int32_t lin_zero_off;      // linearize: write A/B at offset 0 (single-instance outputs)
 };
 
 }  // namespace cord

@@ -167,8 +167,9 @@ __global__ __launch_bounds__(NT) void linearize_kernel(KArgs a) {
     S.solve_step(a.u + I.u_off + (int64_t)t * nu, kb);
 
     if (a.A || a.Bm) {
-        float* A = a.A ? a.A + I.A_off + (int64_t)t * ns * ns : nullptr;
-        float* Bm = a.Bm ? a.Bm + I.B_off + (int64_t)t * ns * nu : nullptr;
+        const int64_t aoff = a.lin_zero_off ? 0 : I.A_off, boff = a.lin_zero_off ? 0 : I.B_off;
+        float* A = a.A ? a.A + aoff + (int64_t)t * ns * ns : nullptr;
+        float* Bm = a.Bm ? a.Bm + boff + (int64_t)t * ns * nu : nullptr;
         float xb[PPT][3], vb[PPT][3], ub[PPT][3];
         for (int r = 0; r < 3 * n; ++r) {
             const int pr = r / 3, cr = r - 3 * pr;

@@ -778,20 +778,25 @@ struct Solver {
             float rp[PPT][NOBS], rc[PPT][NOBS];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
+                // FP32 rounding floor of the force balance grows with the
+                // forces acting on the particle
+                float fm = fmaxf(fabsf(rd[k][0]), fmaxf(fabsf(rd[k][1]), fabsf(rd[k][2])));
 #pragma unroll
                 for (int o = 0; o < NOBS; ++o) {
                     rp[k][o] = 0.f; rc[k][o] = 0.f;
                     if (o < nobs && isfree(k)) {
 #pragma unroll
                         for (int c = 0; c < 3; ++c) rd[k][c] -= cn[k][o][c] * clam[k][o];
+                        fm += fabsf(clam[k][o]);
                         rp[k][o] = cgap[k][o] - cphi[k][o] - dot3(cn[k][o], dl[k]);
                         comp += clam[k][o] * cgap[k][o];
                         err = nmax(err, fabsf(rp[k][o]) / (kTolGap * (h + fabsf(cphi[k][o]))));
                     }
                 }
+                const float tolD = tolF + 5e-7f * fm;
                 if (isfree(k))
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) err = nmax(err, fabsf(rd[k][c]) / tolF);
+                    for (int c = 0; c < 3; ++c) err = nmax(err, fabsf(rd[k][c]) / tolD);
             }
             float mtarget = mu;
             if (hard) {

@@ -1,0 +1,125 @@
+"""Launch modes (grouped, per instance, persistent work queue, hipGraph),
+repeated graph replays, autotuner and a mixed uneven batch (C4-style)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.step import rollout as orollout
+from tests.parity import STATE_TOL, state_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _mixed(seed=600):
+    insts = []
+    for j, n in enumerate((16, 40, 100, 200)):
+        insts += W.small_rope_batch(2, n, 12 + 3 * j, seed=seed + j)
+    for j, side in enumerate((5, 10, 20, 32)):
+        insts += W.small_cloth_batch(1, side, side, 10 + 2 * j, seed=seed + 10 + j)
+    return insts
+
+
+def _setup(insts):
+    import torch
+    from paper_2606_14188_amd import Sim
+    sim = Sim(insts)
+    s0 = sim.pack_states([i.s0 for i in insts])
+    u = sim.pack_controls([i.u for i in insts])
+    sT = sim.pack_states([W.random_cotangent(i.n_s, 40 + j) for j, i in enumerate(insts)])
+    return sim, s0, u, sT
+
+
+def test_launch_modes_bitwise():
+    import torch
+    from paper_2606_14188_amd import _lib as L
+    insts = _mixed()
+    sim, s0, u, sT = _setup(insts)
+    print("classes", sim.classes())
+    ref = sim.rollout(s0, u)
+    rb = sim.backward(u, ref, sT_bar=sT)
+    torch.cuda.synchronize()
+    for mode in (L.LAUNCH_PER_INSTANCE, L.LAUNCH_PERSISTENT, L.LAUNCH_GRAPH):
+        sim.set_launch(mode)
+        for rep in range(2):
+            tr = sim.rollout(s0, u)
+            b = sim.backward(u, tr, sT_bar=sT)
+            torch.cuda.synchronize()
+            assert torch.equal(tr, ref), (mode, rep)
+            assert torch.equal(b[0], rb[0]) and torch.equal(b[1], rb[1]), (mode, rep)
+
+
+def test_graph_replays_with_eager_work_between():
+    import torch
+    from paper_2606_14188_amd import _lib as L
+    insts = _mixed(seed=700)
+    sim, s0, u, sT = _setup(insts)
+    eager = sim.rollout(s0, u).clone()
+    st = torch.full((len(insts),), -1, dtype=torch.int32, device=sim.device)
+    out = torch.empty_like(eager)
+    sim.set_launch(L.LAUNCH_GRAPH)
+    for rep in range(4):
+        out.fill_(float("nan"))            # eager work between replays
+        sim.rollout(s0, u, out=out, status=st)
+        x = torch.randn(1 << 20, device=sim.device).sum()   # more eager work
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        assert (st.cpu().numpy() == 0).all()
+        st.fill_(-1)
+
+
+def test_autotune_and_cache(tmp_path):
+    import torch
+    insts = _mixed(seed=800)
+    sim, s0, u, sT = _setup(insts)
+    path = str(tmp_path / "tune.json")
+    cls = sim.autotune(s0, u, sample=8, cache_path=path)
+    print("tuned", cls)
+    data = json.load(open(path))
+    assert len(data["entries"]) == len(cls)
+    # the chosen configurations still match the oracle
+    tr = sim.rollout(s0, u)
+    torch.cuda.synchronize()
+    parts = sim.split(tr, "traj")
+    for i in (0, 5, 8):
+        ref, _ = orollout(insts[i])
+        ex, ev = state_errors(parts[i], ref, insts[i].n)
+        assert ex <= STATE_TOL and ev <= STATE_TOL, (i, ex, ev)
+    # a second simulator reads the cache and picks the same configurations
+    sim2, *_ = _setup(insts)
+    cls2 = sim2.autotune(s0, u, sample=8, cache_path=path)
+    assert cls2 == cls
+
+
+def test_c4_mixed_batch_graph():
+    """4096 uneven instances (ropes 16..256 nodes, cloths with side capped at
+    32, T 30..120) in one graph launch; sampled instances against the
+    oracle, and one instance alone vs inside the mix (bitwise)."""
+    import torch
+    from paper_2606_14188_amd import _lib as L, Sim
+    insts = W.config_c4(max_cloth_side=32)
+    sim, s0, u, sT = _setup(insts)
+    sim.set_launch(L.LAUNCH_GRAPH)
+    st = torch.full((len(insts),), -1, dtype=torch.int32, device=sim.device)
+    tr = sim.rollout(s0, u, status=st)
+    b = sim.backward(u, tr, sT_bar=sT)
+    torch.cuda.synchronize()
+    stc = st.cpu().numpy()
+    print("classes", sim.classes(), "status", np.bincount(stc, minlength=5))
+    assert (stc == 0).all()
+    parts = sim.split(tr, "traj")
+    small = sorted(range(len(insts)), key=lambda i: insts[i].n * insts[i].T)
+    picks = [i for i in small if insts[i].kind == "rope"][::700][:2] + \
+            [i for i in small if insts[i].kind == "cloth"][::700][:2]
+    for i in picks:
+        ref, _ = orollout(insts[i])
+        ex, ev = state_errors(parts[i], ref, insts[i].n)
+        print(f"C4 instance {i} {insts[i].kind} n={insts[i].n} T={insts[i].T}: x {ex:.2e} v {ev:.2e}")
+        assert ex <= STATE_TOL and ev <= STATE_TOL
+    j = picks[0]
+    alone = Sim([insts[j]])
+    ta = alone.rollout(alone.pack_states([insts[j].s0]), alone.pack_controls([insts[j].u]))
+    torch.cuda.synchronize()
+    assert np.array_equal(alone.split(ta, "traj")[0], parts[j])

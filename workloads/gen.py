@@ -224,17 +224,19 @@ def config_c3(B: int = 256, seed: int = 1003, nx: int = 32, ny: int = 32, T: int
     return [_c3_instance(rng, nx, ny, T) for rng in _streams(seed, B)]
 
 
-def config_c4(B: int = 4096, seed: int = 1004):
+def config_c4(B: int = 4096, seed: int = 1004, max_cloth_side: int = 48, T_range=(30, 120)):
     """Mixed batch: rope (n log-uniform on [16, 256]) or cloth (side
-    log-uniform on [8, 48]) with probability 1/2; T ~ U{30..120}."""
+    log-uniform on [8, 48]) with probability 1/2; T ~ U{30..120}.
+    ``max_cloth_side`` clips the cloth side (the draw itself is unchanged)."""
     out = []
     for rng in _streams(seed, B):
-        T = int(rng.integers(30, 121))
+        T = int(rng.integers(T_range[0], T_range[1] + 1))
         if rng.random() < 0.5:
             n = int(round(math.exp(rng.uniform(math.log(16), math.log(256)))))
             out.append(_c2_instance(rng, n, T))
         else:
             side = int(round(math.exp(rng.uniform(math.log(8), math.log(48)))))
+            side = min(side, max_cloth_side)
             out.append(_c3_instance(rng, side, side, T))
     return out
 
