@@ -80,6 +80,198 @@ def cpu_baseline(workers: int, per_worker: int, T: int, with_lin: bool):
                       f"{' + dense A/B' if with_lin else ''}, {workers} processes, {wall:.1f} s wall"}
 
 
+# ---------------------------------------------------------------- other workloads
+def _time(fn, warmup, steps):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def bench_c3(args):
+    """256 cloths 32x32, T = 60: forward with checkpoints every 10 steps,
+    checkpointed adjoint, and 6 JVP tangents per step (the B_t columns)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2606_14188_amd import Sim, _lib as L
+    insts = W.config_c3()
+    sim = Sim(insts)
+    B, n, T = len(insts), insts[0].n, insts[0].T
+    s0 = sim.pack_states([i.s0 for i in insts])
+    u = sim.pack_controls([i.u for i in insts])
+    sT = sim.pack_states([W.random_cotangent(i.n_s, 8000 + j) for j, i in enumerate(insts)])
+    k = 6
+    du = np.zeros((B, T, k, 6), np.float32)
+    du[:, :, np.arange(6), np.arange(6)] = 1.0
+    dut = torch.from_numpy(du.ravel()).to(sim.device)
+    ck = torch.empty(sim.ckpt_floats(10), dtype=torch.float32, device=sim.device)
+    full = torch.empty(sim.info.traj_floats, dtype=torch.float32, device=sim.device)
+    ms = {}
+
+    def step():
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        e[0].record()
+        sim.rollout(s0, u, store=L.STORE_CKPT, ckpt_every=10, out=ck)
+        e[1].record()
+        sim.backward(u, ck, sT_bar=sT, store=L.STORE_CKPT, ckpt_every=10)
+        e[2].record()
+        sim.rollout(s0, u, out=full)
+        e[3].record()
+        sim.linearize(full, u, dense=False, want_B=False, jvp_k=k, jvp_du=dut)
+        e[4].record()
+        step.ev.append(e)
+    step.ev = []
+    tms = _time(step, args.warmup, args.steps)
+    ev = step.ev[args.warmup:]
+    names = ["rollout_ckpt", "backward_ckpt", "rollout_full", "jvp6"]
+    for j, nm in enumerate(names):
+        ms[nm] = float(np.mean([x[j].elapsed_time(x[j + 1]) for x in ev]))
+    ps = B * n * T
+    print(json.dumps({"workload": "cloth-32x32 x 256, T=60: forward (ckpt 10) + checkpointed adjoint + 6 JVP tangents/step",
+                      "ms_per_step": tms, "particle_steps_per_s": ps / (tms / 1e3), "kernel_ms": ms,
+                      "fwd_bwd_particle_steps_per_s": ps / ((ms["rollout_ckpt"] + ms["backward_ckpt"]) / 1e3)}), flush=True)
+
+
+def bench_c4(args):
+    """4096 mixed ropes/cloths (cloth side capped at 32), forward + adjoint,
+    as one hipGraph of persistent per-class launches vs one launch per
+    instance."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2606_14188_amd import Sim, _lib as L
+    insts = W.config_c4(max_cloth_side=32)
+    sim = Sim(insts)
+    s0 = sim.pack_states([i.s0 for i in insts])
+    u = sim.pack_controls([i.u for i in insts])
+    sT = sim.pack_states([W.random_cotangent(i.n_s, 9000 + j) for j, i in enumerate(insts)])
+    traj = torch.empty(sim.info.traj_floats, dtype=torch.float32, device=sim.device)
+    ps = sum(i.n * i.T for i in insts)
+    out = {"workload": "C4 mixed: 4096 instances (ropes 16..256, cloths 8x8..32x32), T 30..120, forward + adjoint",
+           "particle_steps": ps}
+    if args.autotune:
+        out["tuned"] = sim.autotune(s0, u, sample=64)
+    out["classes"] = sim.classes()
+    for name, mode in (("graph", L.LAUNCH_GRAPH), ("persistent", L.LAUNCH_PERSISTENT),
+                       ("grouped", L.LAUNCH_GROUPED), ("per_instance", L.LAUNCH_PER_INSTANCE)):
+        sim.set_launch(mode)
+
+        def step():
+            sim.rollout(s0, u, out=traj)
+            sim.backward(u, traj, sT_bar=sT)
+        tms = _time(step, 1, max(1, args.steps // 2))
+        out[name] = {"ms_per_step": tms, "particle_steps_per_s": ps / (tms / 1e3)}
+        print(name, out[name], file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+def bench_probe(args):
+    """Context probe at batch 1: one step of a 20-node rope and of a 10x10
+    cloth, forward alone and the dense step Jacobian (A_t, B_t), each the
+    median of repeated launches.  The paper's simulator-speed table quotes
+    the same shapes on unstated hardware; it is context, not a target."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2606_14188_amd import Sim
+    rope = W.config_c1().replace(T=1)
+    rope = rope.replace(u=rope.u[:1])
+    cloth = W.small_cloth_batch(1, 10, 10, 1, seed=1006)[0]
+    out = {"workload": "batch-1 probe: one step of a 20-node rope and of a 10x10 cloth (forward; dense A_t/B_t)",
+           "paper_context_ms": {"rope": {"forward": 1.095, "jacobian": 5.198},
+                                "cloth": {"forward": 15.08, "jacobian": 10.06},
+                                "note": "paper's table, hardware not stated; forward may be a rollout"}}
+    for name, inst in (("rope", rope), ("cloth", cloth)):
+        sim = Sim([inst])
+        s0 = sim.pack_states([inst.s0])
+        u = sim.pack_controls([inst.u])
+        traj = sim.rollout(s0, u)
+        A, Bm, _ = sim.linearize(traj, u)
+        times = {"forward": [], "jacobian": []}
+        for _ in range(max(20, args.steps)):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record()
+            sim.rollout(s0, u, out=traj)
+            e[1].record()
+            sim.linearize(traj, u, A=A, Bm=Bm)
+            e[2].record()
+            torch.cuda.synchronize()
+            times["forward"].append(e[0].elapsed_time(e[1]))
+            times["jacobian"].append(e[1].elapsed_time(e[2]))
+        out[name] = {k: float(np.median(v)) for k, v in times.items()}
+        out[name]["n"] = inst.n
+    print(json.dumps(out), flush=True)
+
+
+def _serve_once(trace, slots):
+    """Replay a request trace against one server; latencies are measured from
+    each request's scheduled arrival (so a slow submit counts against the
+    server) to the moment its result is ready."""
+    import threading
+    import numpy as np
+    from paper_2606_14188_amd.serve import Server
+    srv = Server(hbm_budget=64 << 30, max_slots=slots, queue_cap=1 << 20)
+    tickets, late = [], []
+
+    def submitter():
+        t0 = time.perf_counter()
+        for (ta, inst, gn, goal) in trace:
+            dt = ta - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            late.append(max(0.0, time.perf_counter() - t0 - ta))
+            tickets.append(srv.submit(inst, goal_node=gn, goal=goal, n_cand=128, iters=10, step=0.05,
+                                      sigma=0.05, seed=len(tickets), want_AB=(inst.kind == "rope"), u_warm=inst.u))
+    t_start = time.perf_counter()
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    lat, fails = [], 0
+    for t, lt in zip(tickets, late):
+        r = srv.wait(t, 600000)
+        lat.append(lt + r.latency)
+        fails += int(r.status != 0 or r.sim_status != 0)
+        srv.release(t)
+    wall = time.perf_counter() - t_start
+    st = srv.stats()
+    srv.close()
+    lat = np.array(lat) * 1e3
+    return {"slots": slots, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "throughput_req_s": len(trace) / wall, "wall_s": wall,
+            "drain_s": wall - trace[-1][0],
+            "peak_queue": st["peak_queue"], "failed_or_flagged": fails}
+
+
+def bench_c5(args, rates=(200.0, 15.0), quiet=False):
+    """Served planning stream: Poisson arrivals, each request 128 candidates
+    x T=30 x 10 gradient steps on a rope (48..128) or cloth (16x16..32x32),
+    plus A_t/B_t along the winner for ropes.  Continuous batching (8 slots)
+    vs one request at a time, on the same trace, at the offered rate and at
+    a rate below the batched server's capacity."""
+    import workloads as W
+    out = {"workload": "planning stream: Poisson arrivals, 128 candidates x T=30 x 10 gradient steps, "
+                       "ropes 48..128 (+A_t/B_t) / cloths 16x16..32x32"}
+    for rate in rates:
+        duration = args.serve_seconds if rate >= 100 else max(4.0, 4 * args.serve_seconds)
+        trace = W.serve_trace(rate, duration)
+        res = {"offered_req_s": rate, "duration_s": duration, "requests": len(trace)}
+        for name, slots in (("batched", 8), ("plain", 1)):
+            res[name] = _serve_once(trace, slots)
+            if not quiet:
+                print(rate, name, res[name], file=sys.stderr, flush=True)
+        # backlog left when the last request arrives: about one request's
+        # latency if the server keeps up with the offered rate
+        res["batched_keeps_up"] = bool(res["batched"]["drain_s"] < 1.0)
+        out[f"rate_{rate:g}"] = res
+    return out
+
+
 # ---------------------------------------------------------------- GPU
 def main():
     ap = argparse.ArgumentParser()
@@ -91,11 +283,25 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=8)
     ap.add_argument("--cpu-per-worker", type=int, default=1)
     ap.add_argument("--cpu-T", type=int, default=25)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "probe"])
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--no-serve", action="store_true", help="skip the short planning-stream leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); instances are independent "
               "and would shard by instance across GPUs, which this build does not launch.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c3":
+        return bench_c3(args)
+    if args.workload == "c4":
+        return bench_c4(args)
+    if args.workload == "probe":
+        return bench_probe(args)
+    if args.workload == "c5":
+        print(json.dumps(bench_c5(args)), flush=True)
+        return
 
     with_lin = not args.no_linearize
     cpu = None
@@ -187,6 +393,11 @@ def main():
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
     roof["kernel"] = dom
+    serve = None
+    if not args.no_serve:
+        del A, Bm
+        torch.cuda.empty_cache()
+        serve = bench_c5(args, quiet=True)
     out = {
         "metric": "particle-steps/s fwd+bwd (rope/cloth batch); MPC plan p50/p99 ms vs plain",
         "value": value,
@@ -208,6 +419,7 @@ def main():
         "status_nonzero": int((st != 0).sum()),
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serve": serve,
     }
     print(json.dumps(out), flush=True)
 

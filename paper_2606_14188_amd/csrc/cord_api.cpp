@@ -52,6 +52,33 @@ namespace cord {
 const int kRopeBuckets[] = {32, 64, 128, 256};
 const int kClothBuckets[] = {64, 128, 256, 512, 1024};
 
+// Dense A_t/B_t of rope classes go to the banded direct kernel; JVPs, cloth,
+// B_t alone and classes it does not cover use the class's iterative kernel.
+// Setting CORD_LINEARIZE_ITERATIVE=1 in the environment forces the iterative
+// kernel everywhere (for comparisons).
+hipError_t launch_linearize(int cfg_index, int topo, int nmax, const KArgs& a, int nblk, int tmax, hipStream_t st) {
+    static const bool iterative = [] {
+        const char* e = std::getenv("CORD_LINEARIZE_ITERATIVE");
+        return e && e[0] == '1';
+    }();
+    int count = 0;
+    const KernelCfg* cfg = kernel_configs(&count);
+    if (a.A && topo == kRope && !iterative) {
+        KArgs ad = a;
+        ad.jvp_k = 0; ad.jvp_ds = nullptr; ad.jvp_du = nullptr; ad.jvp_out = nullptr;
+        bool handled = false;
+        hipError_t e = linearize_rope_direct(nmax, ad, nblk, tmax, st, &handled);
+        if (e != hipSuccess) return e;
+        if (handled) {
+            if (!a.jvp_out) return hipSuccess;
+            KArgs aj = a;
+            aj.A = nullptr; aj.Bm = nullptr;
+            return cfg[cfg_index].linearize(aj, nblk, tmax, st);
+        }
+    }
+    return cfg[cfg_index].linearize(a, nblk, tmax, st);
+}
+
 int bucket_of(int topo, int n) {
     const int* b = topo == kRope ? kRopeBuckets : kClothBuckets;
     const int nb = topo == kRope ? 4 : 5;
@@ -621,12 +648,10 @@ int cord_linearize(cord_sim* s, const float* traj, const float* u, float* A, flo
     if (jvp) { a.jvp_k = jvp->k; a.jvp_ds = jvp->ds; a.jvp_du = jvp->du; a.jvp_out = jvp->out; }
     hipStream_t st = (hipStream_t)stream;
     if (inst_status) CORD_HIP(launch_fill_i32(inst_status, s->info.n_inst, 0, st));
-    int count = 0;
-    const KernelCfg* cfg = kernel_configs(&count);
     for (const Group& g : s->groups) {
         a.ids = g.d_ids;
         a.n_ids = (int)g.ids.size();
-        CORD_HIP(cfg[g.cfg].linearize(a, a.n_ids, g.tmax, st));
+        CORD_HIP(launch_linearize(g.cfg, g.topo, g.nmax, a, a.n_ids, g.tmax, st));
     }
     return CORD_OK;
 }

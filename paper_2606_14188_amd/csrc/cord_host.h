@@ -10,4 +10,6 @@ int bucket_of(int topo, int n);
 int default_config(int topo, int nmax);
 int set_error(int code, const char* msg);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+struct KArgs;
+hipError_t launch_linearize(int cfg_index, int topo, int nmax, const KArgs& a, int nblk, int tmax, hipStream_t st);
 }  // namespace cord

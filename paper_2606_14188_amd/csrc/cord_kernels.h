@@ -21,4 +21,10 @@ struct KernelCfg {
 
 const KernelCfg* kernel_configs(int* count);
 
+// Dense A_t (and B_t) of ropes by banded direct solves, for size classes up
+// to 128 particles.  Sets *handled = false (and launches nothing) for other
+// classes or if the device's LDS is too small; the caller then uses the
+// class's iterative linearize kernel.
+hipError_t linearize_rope_direct(int nmax, const KArgs& a, int nblk, int tmax, hipStream_t s, bool* handled);
+
 }  // namespace cord

@@ -1,0 +1,491 @@
+// Dense per-step linearization of ropes by banded direct solves.
+//
+// For a rope every operator of the step derivative (the stage-1 Hessian H,
+// the stage-2 matrix K = H + N^T Lam N and J = H - W + C - R of eq.
+// (diff-sim)) couples a particle only with its neighbours up to distance 2
+// (stretch springs at distance 1, the bending stencil at distance 2).  In the
+// 3n scalar unknowns each is a band matrix of half-bandwidth 8, so one
+// workgroup per (instance, step) recomputes the step, assembles the bands
+// in LDS, factors H_ff = L L^T and K_ff = U U^T (U upper triangular: the
+// Cholesky factor of the index-reversed matrix) with one wavefront each,
+// and then every lane solves for one column j of the step map on its own.
+//
+// Column j is the response E = dx+ - z to the unit predictor tangent z = e_j
+// (z is dxhat on free particles and the gripper displacement db on gripped
+// ones).  With the increments of the tangent map
+//     eps = -H_ff^{-1} (H_el z)_f,   E = K_ff^{-1} (J_ff eps + Qhat z),
+//     Qhat = (J - K)_ff on free columns, -W_fg on gripped columns,
+// so E never forms dx+ - z by cancellation.  Three sweeps over the rows:
+//   1 (ascending)  w1 = L^{-1} r1         (r1 = -(H_el z)_f is local to j)
+//   2 (descending) eps = L^{-T} w1, r = J eps + Qhat z (lagging 8 rows),
+//                  w2 = U^{-1} r          (U is upper: also descending)
+//   3 (ascending)  E = U^{-T} w2, written out as the A_t (and B_t) columns.
+// Choosing U U^T for K makes its first triangular solve run in the same
+// direction as the second solve with L, so one vector per column (w1, then
+// w2 in its place) is all that must be kept between sweeps.  It is kept in
+// the column's own slot of the dv+/dv block of A_t, which sweep 3 overwrites
+// with the final value.  The band factors, J and the right-hand-side
+// stencils sit in LDS and are read at wave-uniform addresses (broadcast).
+//
+// Outputs for column j (dx+ rows first, then dv+ rows; d_ij = [i == j]):
+//   A[i][j] = d_ij + E_i,  A[3n+i][j] = E_i / dt,
+//   j free:    A[i][3n+j] = dt(1-gamma)(d_ij + E_i), A[3n+i][3n+j] = (1-gamma)(d_ij + E_i)
+//   j gripped: A[.][3n+j] = 0, B[i][g] = dt (d_ij + E_i), B[3n+i][g] = d_ij + E_i.
+#pragma once
+#include "cord_solver.h"
+
+namespace cord {
+
+constexpr int kBand = 8;   // half-bandwidth of H, K, J in scalar unknowns
+constexpr int kRing = 32;  // rows per unrolled block of a sweep (ring size)
+constexpr int kPf = 16;    // rows of prefetch distance for the kept vector
+
+// LDS carve-up (floats, after the solver's own LDS) for up to 3*NMAX rows.
+template <int NMAX>
+struct LinLds {
+    static constexpr int N3 = 3 * NMAX;
+    static constexpr int LC = 0;                  // L(k+m, k), m = 1..8   [k][8]
+    static constexpr int LI = LC + N3 * 8;        // 1 / L(k, k)
+    static constexpr int UW = LI + N3;            // U(i-m, i) at [N-1-i][m-1]
+    static constexpr int UD = UW + N3 * 8;        // 1 / U(i, i) at [N-1-i]
+    static constexpr int HB = UD + N3;            // H(i, i-m), m = 0..8   [i][9]
+    static constexpr int JB = HB + N3 * 9;        // J(i, i-8+q), q = 0..16 [i][20]
+    static constexpr int NL = JB + N3 * 20;       // (w n n^T) row i, same-particle columns [i][3]
+    static constexpr int RF = NL + N3 * 3;        // 1 if row i is free
+    static constexpr int TOTAL = RF + N3;
+};
+
+__device__ __forceinline__ void sym_to_full(const float s[6], float m[3][3]) {
+    m[0][0] = s[0]; m[0][1] = s[1]; m[0][2] = s[2];
+    m[1][0] = s[1]; m[1][1] = s[3]; m[1][2] = s[4];
+    m[2][0] = s[2]; m[2][1] = s[4]; m[2][2] = s[5];
+}
+
+// Banded Cholesky (half-bandwidth 8) by one wavefront, in place:
+// C[k][m-1] = A(k+m, k) -> L(k+m, k),  Dg[k] = A(k, k) -> 1 / L(k, k).
+// Right-looking: step k scales column k (lanes 1..8) and updates the 36
+// entries of the trailing 8x8 window (one lane each).  Steps depend on each
+// other only through LDS, whose reads and writes a wavefront performs in
+// program order.  Returns false if a pivot was not positive (it is then
+// replaced by 1 so that the sweeps stay finite).
+__device__ __forceinline__ bool band_cholesky(float* C, float* Dg, int N) {
+    const int lane = (int)threadIdx.x & 63;
+    // lanes 0..35 -> (a, b), 1 <= a <= b <= 8, column-major over b
+    int ua = 0, ub = 0;
+    {
+        int idx = lane, b = 1;
+        while (b <= kBand && idx >= b) { idx -= b; ++b; }
+        ub = b;
+        ua = idx + 1;
+    }
+    const bool upd = lane < 36;
+    const bool scl = lane >= 1 && lane <= kBand;
+    bool ok = true;
+    for (int k = 0; k < N; ++k) {
+        float d = Dg[k];
+        if (!(d > 0.f)) { ok = false; d = 1.f; }
+        const float is = 1.0f / sqrtf(d);
+        float la = 0.f, lb = 0.f, lm = 0.f;
+        if (upd && k + ub < N) {
+            la = C[k * 8 + ua - 1] * is;
+            lb = C[k * 8 + ub - 1] * is;
+        }
+        if (scl && k + lane < N) lm = C[k * 8 + lane - 1] * is;
+        __builtin_amdgcn_wave_barrier();
+        if (scl) C[k * 8 + lane - 1] = lm;
+        if (lane == 0) Dg[k] = is;
+        if (upd && k + ub < N) {
+            if (ua == ub) Dg[k + ua] -= la * la;
+            else C[(k + ua) * 8 + (ub - ua) - 1] -= la * lb;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    return ok;
+}
+
+template <int NT, int NMAX, int NOBS>
+__global__ __launch_bounds__(NT) void linearize_direct_kernel(KArgs a) {
+    static_assert(NT % 64 == 0 && NT >= 3 * NMAX && NT >= 128, "one lane per column, two factor waves");
+    using LL = LinLds<NMAX>;
+    extern __shared__ float lds[];
+    const int id = a.ids[blockIdx.x];
+    const InstDev& I = a.inst[id];
+    const int t = blockIdx.y;
+    if (t >= I.T) return;
+    Solver<kRope, NT, 1, NOBS> S;
+    S.init(I, lds);
+    const int n = I.n, ns = I.n_s, nu = I.n_u, N = 3 * n;
+    const float kap = I.kappa_bwd, dt = I.dt, idt = 1.0f / I.dt, gam = I.gamma, mdt2 = S.mdt2;
+    S.load_state(a.traj_in + I.traj_off + (int64_t)t * ns);
+    S.solve_step(a.u + I.u_off + (int64_t)t * nu, kap);
+
+    float* B = lds + lds_floats<NT, 1>();
+    float* LC = B + LL::LC;
+    float* LI = B + LL::LI;
+    float* UW = B + LL::UW;
+    float* UD = B + LL::UD;
+    float* HB = B + LL::HB;
+    float* JB = B + LL::JB;
+    float* NL = B + LL::NL;
+    float* RF = B + LL::RF;
+
+    // ---------------------------------------------------------- assembly
+    // Thread p < n writes rows 3p..3p+2 of every band.  Blocks of particle p
+    // (3x3): spring blocks K_s = sa e e^T + sb I (slot 0: p+1, slot 1: p-1),
+    // bending couplings kb * (stencil^T stencil), third-derivative blocks W_s,
+    // contact C_p, R_p = w n (H_phi D)^T and N^T Lam N (free particles).
+    {
+        const int p = threadIdx.x;
+        const bool live = p < n;
+        const bool fr = live && S.isfree(0);
+        float Ks[2][6], Ws[2][6];
+        float Cp[3][3], Rp[3][3], NLq[6], NLk[6];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int e = 0; e < 6; ++e) { Ks[s][e] = 0.f; Ws[s][e] = 0.f; }
+#pragma unroll
+        for (int e = 0; e < 6; ++e) { NLq[e] = 0.f; NLk[e] = 0.f; }
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { Cp[r][c] = 0.f; Rp[r][c] = 0.f; }
+        if (live) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int q = S.nbr(0, p, s);
+                if (q < 0) continue;
+                sym_add_outer(Ks[s], S.sa[0][s], S.se[0][s]);
+                Ks[s][0] += S.sb[0][s]; Ks[s][3] += S.sb[0][s]; Ks[s][5] += S.sb[0][s];
+                // W_s = cw (eD I + De e^T + e De^T - 3 eD e e^T / L^2)
+                float e[3], De[3], Dp[3];
+                S.get(S.DL, p, Dp);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    e[c] = (S.X[c * NT + q] - S.x[0][c]) + (S.D[c * NT + q] - S.d[0][c]);
+                    De[c] = S.DL[c * NT + q] - Dp[c];
+                }
+                const float L2 = dot3(e, e);
+                const float il = 1.0f / sqrtf(L2);
+                const float cw = S.kS[0] * S.rS[0] * il * il * il;
+                const float eD = dot3(e, De);
+                float m[3][3];
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        m[r][c] = cw * ((r == c ? eD : 0.f) + De[r] * e[c] + e[r] * De[c] - 3.f * eD * e[r] * e[c] / L2);
+                Ws[s][0] = m[0][0]; Ws[s][1] = m[0][1]; Ws[s][2] = m[0][2];
+                Ws[s][3] = m[1][1]; Ws[s][4] = m[1][2]; Ws[s][5] = m[2][2];
+            }
+            if (fr) {
+                const float yst[3] = {S.x[0][0] + S.d[0][0], S.x[0][1] + S.d[0][1], S.x[0][2] + S.d[0][2]};
+#pragma unroll
+                for (int o = 0; o < NOBS; ++o) {
+                    if (o >= S.nobs) continue;
+                    float Hc[6], hd[3], Hm[3][3];
+                    sdf_hess(S.otype[o], S.ob[o], yst, Hc);
+                    sym_mul(Hc, S.dl[0], hd);
+                    sym_to_full(Hc, Hm);
+                    const float lam = S.clam[0][o], gap = S.cgap[0][o];
+                    const float wk = lam / gap;
+                    const float w = kap > 0.f ? wk : 0.f;
+                    const float* nn = S.cn[0][o];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            Cp[r][c] += lam * Hm[r][c];
+                            Rp[r][c] += w * nn[r] * hd[c];
+                        }
+                    sym_add_outer(NLq, w, nn);
+                    sym_add_outer(NLk, wk, nn);
+                }
+            }
+        }
+        // bending: particle c in [1, n-2] carries the stencil (1, -2, 1)
+        const float kb = S.kb;
+        auto inR = [&](int c) { return (c >= 1 && c <= n - 2) ? 1.f : 0.f; };
+        const float bd0 = kb * (inR(p - 1) + 4.f * inR(p) + inR(p + 1));
+        const float bm1 = -2.f * kb * (inR(p - 1) + inR(p));     // (p, p-1)
+        const float bp1 = -2.f * kb * (inR(p) + inR(p + 1));     // (p, p+1)
+        const float bm2 = kb * inR(p - 1);                        // (p, p-2)
+        const float bp2 = kb * inR(p + 1);                        // (p, p+2)
+        // H block (p, p+dq)[r][c], dq in -2..2
+        auto Hblk = [&](int dq, int r, int c) -> float {
+            const float I3 = (r == c) ? 1.f : 0.f;
+            float ks[3][3];
+            if (dq == 0) {
+                float v = (fr ? mdt2 : 0.f) * I3 + bd0 * I3;
+                sym_to_full(Ks[0], ks); v += ks[r][c];
+                sym_to_full(Ks[1], ks); v += ks[r][c];
+                return v;
+            }
+            if (dq == 1) { sym_to_full(Ks[0], ks); return -ks[r][c] + bp1 * I3; }
+            if (dq == -1) { sym_to_full(Ks[1], ks); return -ks[r][c] + bm1 * I3; }
+            if (dq == 2) return bp2 * I3;
+            return bm2 * I3;
+        };
+        auto Wblk = [&](int dq, int r, int c) -> float {
+            float ws[3][3];
+            if (dq == 0) {
+                float v = 0.f;
+                sym_to_full(Ws[0], ws); v += ws[r][c];
+                sym_to_full(Ws[1], ws); v += ws[r][c];
+                return v;
+            }
+            if (dq == 1) { sym_to_full(Ws[0], ws); return -ws[r][c]; }
+            if (dq == -1) { sym_to_full(Ws[1], ws); return -ws[r][c]; }
+            return 0.f;
+        };
+        if (live) {
+            int gq[kMaxGrip];
+#pragma unroll
+            for (int g = 0; g < kMaxGrip; ++g) gq[g] = g < I.n_grip ? I.grip_node[g] : -1;
+            auto is_free = [&](int q) {
+                bool f = true;
+#pragma unroll
+                for (int g = 0; g < kMaxGrip; ++g) f = f && (gq[g] != q);
+                return f;
+            };
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int i = 3 * p + r;
+                RF[i] = fr ? 1.f : 0.f;
+                {
+                    float nq[3][3];
+                    sym_to_full(NLq, nq);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) NL[i * 3 + c] = nq[r][c];
+                }
+                float nk[3][3];
+                sym_to_full(NLk, nk);
+                // lower band of H (full coupling), of H_ff and (reversed) K_ff
+#pragma unroll
+                for (int m = 0; m <= kBand; ++m) {
+                    const int k = i - m;
+                    // column k = 3(p + dq) + c with dq, c fixed by r and m
+                    const int off = r - m;
+                    const int dq = off >= 0 ? off / 3 : -((2 - off) / 3);
+                    const int c = off - 3 * dq;
+                    float hv = 0.f, hf = 0.f, kf = 0.f;
+                    if (k >= 0) {
+                        hv = Hblk(dq, r, c);
+                        const bool cf = is_free(p + dq);
+                        if (fr && cf) {
+                            hf = hv;
+                            kf = hv + (dq == 0 ? nk[r][c] : 0.f);
+                        } else {
+                            hf = (m == 0) ? 1.f : 0.f;
+                            kf = hf;
+                        }
+                    }
+                    HB[i * 9 + m] = hv;
+                    if (m == 0) {
+                        LI[i] = hf;
+                        UD[N - 1 - i] = kf;
+                    } else {
+                        if (k >= 0) LC[k * 8 + m - 1] = hf;
+                        UW[(N - 1 - i) * 8 + m - 1] = kf;
+                    }
+                }
+                // J row (free rows; zero on gripped rows)
+#pragma unroll
+                for (int qq = 0; qq <= 2 * kBand; ++qq) {
+                    const int k = i - kBand + qq;
+                    const int off = r - kBand + qq;
+                    const int dq = off >= 0 ? off / 3 : -((2 - off) / 3);
+                    const int c = off - 3 * dq;
+                    float jv = 0.f;
+                    if (fr && k >= 0 && k < N) {
+                        jv = Hblk(dq, r, c) - Wblk(dq, r, c) + (dq == 0 ? Cp[r][c] - Rp[r][c] : 0.f);
+                    }
+                    JB[i * 20 + qq] = jv;
+                }
+            }
+        }
+        // entries that reach past the last row: L(k+m, k) with k+m >= N and
+        // U(i-m, i) with i-m < 0 are zero
+        if (live) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int k = 3 * p + r;
+#pragma unroll
+                for (int m = 1; m <= kBand; ++m) {
+                    if (k + m >= N) LC[k * 8 + m - 1] = 0.f;
+                    if (k - m < 0) UW[(N - 1 - k) * 8 + m - 1] = 0.f;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // ---------------------------------------------------------- factorizations
+    {
+        const int wv = threadIdx.x >> 6;
+        bool ok = true;
+        if (wv == 0) ok = band_cholesky(LC, LI, N);
+        else if (wv == 1) ok = band_cholesky(UW, UD, N);
+        if (!ok && (threadIdx.x & 63) == 0 && a.status) atomicMax(&a.status[id], kStNotPD);
+    }
+    __syncthreads();
+
+    // ---------------------------------------------------------- column sweeps
+    const int j = threadIdx.x;
+    const bool jok = j < N;
+    if (a.A && jok) {
+        const int64_t aoff = a.lin_zero_off ? 0 : I.A_off, boff = a.lin_zero_off ? 0 : I.B_off;
+        float* At = a.A + aoff + (int64_t)t * ns * ns;
+        float* Bt = a.Bm ? a.Bm + boff + (int64_t)t * ns * nu : nullptr;
+        float* Sv = At + (int64_t)N * ns + N + j;     // kept vector: column j of the dv+/dv block
+        const int pj = j / 3, cj = j - 3 * pj;
+        const bool fj = RF[j] != 0.f;
+        int gj = -1;
+        for (int g = 0; g < I.n_grip; ++g)
+            if (I.grip_node[g] == pj) gj = g;
+        const int i0 = max(0, (int)(threadIdx.x & ~63) - kBand);
+
+        // sweep 1: w1 = L^{-1} r1, rows i0..N-1
+        {
+            float w[kRing];
+#pragma unroll
+            for (int u = 0; u < kRing; ++u) w[u] = 0.f;
+            for (int tb = 0; i0 + tb < N; tb += kRing) {
+#pragma unroll
+                for (int u = 0; u < kRing; ++u) {
+                    const int i = i0 + tb + u;
+                    if (i < N) {
+                        const int dd = i - j;
+                        float r1 = 0.f;
+                        if (dd >= -kBand && dd <= kBand && RF[i] != 0.f) {
+                            const float h = dd >= 0 ? HB[i * 9 + dd] : HB[j * 9 - dd];
+                            r1 = -(h - (dd == 0 ? mdt2 : 0.f));
+                        }
+                        float acc = r1;
+#pragma unroll
+                        for (int m = 1; m <= kBand; ++m)
+                            if (i - m >= i0) acc -= LC[(i - m) * 8 + m - 1] * w[(u - m + kRing) % kRing];
+                        const float wi = acc * LI[i];
+                        w[u] = wi;
+                        Sv[(int64_t)i * ns] = wi;
+                    }
+                }
+            }
+        }
+        // sweep 2 (descending, position s = N-1-i): eps, r (8 rows behind), w2
+        {
+            float e[kRing], w2[kRing], pf[kRing];
+#pragma unroll
+            for (int u = 0; u < kRing; ++u) { e[u] = 0.f; w2[u] = 0.f; pf[u] = 0.f; }
+#pragma unroll
+            for (int u = 0; u < kPf; ++u) {
+                const int i = N - 1 - u;
+                pf[u] = (i >= i0) ? Sv[(int64_t)i * ns] : 0.f;
+            }
+            for (int sb = 0; sb < N + kBand; sb += kRing) {
+#pragma unroll
+                for (int u = 0; u < kRing; ++u) {
+                    const int s = sb + u;
+                    const int i = N - 1 - s;
+                    if (s < N + kBand) {
+                        // prefetch the kept value kPf rows ahead
+                        {
+                            const int ip = i - kPf;
+                            if (ip >= i0) pf[(u + kPf) % kRing] = Sv[(int64_t)ip * ns];
+                        }
+                        float ei = 0.f;
+                        if (i >= 0) {
+                            float acc = (i >= i0) ? pf[u] : 0.f;
+#pragma unroll
+                            for (int m = 1; m <= kBand; ++m) acc -= LC[i * 8 + m - 1] * e[(u - m + kRing) % kRing];
+                            ei = acc * LI[i];
+                        }
+                        e[u] = ei;
+                        const int mrow = i + kBand;
+                        if (mrow < N) {
+                            float r = 0.f;
+                            if (RF[mrow] != 0.f) {
+                                // e[(u - 16 + qq)] holds eps_{mrow - 8 + qq}
+#pragma unroll
+                                for (int qq = 0; qq <= 2 * kBand; ++qq)
+                                    r += JB[mrow * 20 + qq] * e[(u - qq + kRing) % kRing];
+                                const int dq = j - mrow;
+                                if (dq >= -kBand && dq <= kBand) {
+                                    const float jv = JB[mrow * 20 + kBand + dq];
+                                    const float hv = dq <= 0 ? HB[mrow * 9 - dq] : HB[j * 9 + dq];
+                                    const bool same = (mrow / 3) == pj;
+                                    const float nv = (same && fj) ? NL[mrow * 3 + cj] : 0.f;
+                                    r += jv - hv - nv;
+                                }
+                            }
+                            float acc = r;
+#pragma unroll
+                            for (int q = 1; q <= kBand; ++q)
+                                if (mrow + q < N) acc -= UW[(N - 1 - mrow - q) * 8 + q - 1] * w2[(u - q + kRing) % kRing];
+                            const float wv = acc * UD[N - 1 - mrow];
+                            w2[u] = wv;
+                            Sv[(int64_t)mrow * ns] = wv;
+                        } else {
+                            w2[u] = 0.f;
+                        }
+                    }
+                }
+            }
+        }
+        // sweep 3 (ascending): E = U^{-T} w2 and the outputs
+        {
+            float E[kRing], pf[kRing];
+#pragma unroll
+            for (int u = 0; u < kRing; ++u) { E[u] = 0.f; pf[u] = 0.f; }
+#pragma unroll
+            for (int u = 0; u < kPf; ++u)
+                if (u < N) pf[u] = Sv[(int64_t)u * ns];
+            const float c1 = dt * (1.f - gam), omg = 1.f - gam;
+            for (int tb = 0; tb < N; tb += kRing) {
+#pragma unroll
+                for (int u = 0; u < kRing; ++u) {
+                    const int i = tb + u;
+                    if (i < N) {
+                        {
+                            const int ip = i + kPf;
+                            if (ip < N) pf[(u + kPf) % kRing] = Sv[(int64_t)ip * ns];
+                        }
+                        float acc = pf[u];
+#pragma unroll
+                        for (int q = 1; q <= kBand; ++q)
+                            acc -= UW[(N - 1 - i) * 8 + q - 1] * E[(u - q + kRing) % kRing];
+                        const float Ei = acc * UD[N - 1 - i];
+                        E[u] = Ei;
+                        const float dx = (i == j ? 1.f : 0.f) + Ei;
+                        At[(int64_t)i * ns + j] = dx;
+                        At[(int64_t)(N + i) * ns + j] = Ei * idt;
+                        if (fj) {
+                            At[(int64_t)i * ns + N + j] = c1 * dx;
+                            At[(int64_t)(N + i) * ns + N + j] = omg * dx;
+                        } else {
+                            At[(int64_t)i * ns + N + j] = 0.f;
+                            At[(int64_t)(N + i) * ns + N + j] = 0.f;
+                            if (Bt && gj >= 0) {
+                                Bt[(int64_t)i * nu + 3 * gj + cj] = dt * dx;
+                                Bt[(int64_t)(N + i) * nu + 3 * gj + cj] = dx;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (threadIdx.x == 0 && a.status) atomicMax(&a.status[id], S.status);
+    if (threadIdx.x == 0 && a.counters)
+        for (int i = 0; i < 4; ++i) atomicAdd(&a.counters[4 * id + i], S.cnt[i]);
+}
+
+template <int NT, int NMAX, int NOBS>
+struct LinDirect {
+    static constexpr size_t kLds = sizeof(float) * (lds_floats<NT, 1>() + LinLds<NMAX>::TOTAL);
+    static hipError_t launch(const KArgs& a, int nblk, int tmax, hipStream_t s) {
+        hipLaunchKernelGGL((linearize_direct_kernel<NT, NMAX, NOBS>), dim3(nblk, tmax), dim3(NT), kLds, s, a);
+        return hipGetLastError();
+    }
+};
+
+}  // namespace cord

@@ -6,8 +6,14 @@
 // not fit may be overtaken by at most kSkipAhead later ones).  Device memory
 // is sub-allocated from one arena reserved at start, so admission and
 // completion never call hipMalloc/hipFree (which would synchronise the device
-// and serialise the slots).  Completion is detected by polling one event per
-// request; results are then copied to host buffers owned by the server.
+// and serialise the slots).  Each slot owns pinned host staging: uploads and
+// the result download are asynchronous copies on the slot's stream, queued
+// with the request's kernels, so the scheduler never waits on the device.
+// Completion is detected by polling one event per request; results are then
+// copied from the slot's staging to host buffers owned by the request.  The
+// server mutex guards only the queues and counters: staging, uploads, kernel
+// launches and result copies run without it, so submit/poll/wait never wait
+// for device work.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -135,6 +141,63 @@ uint64_t splitmix64(uint64_t& x) {
 }
 double unit_open(uint64_t& x) { return ((double)(splitmix64(x) >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
 
+// Pinned host staging of one slot, grown on demand (only while the slot is
+// idle, so no copy on its stream can still be reading or writing it).
+struct Staging {
+    char* up = nullptr;
+    size_t up_cap = 0;
+    char* down = nullptr;
+    size_t down_cap = 0;
+};
+
+bool grow_pinned(char** p, size_t* cap, size_t need) {
+    if (need <= *cap) return true;
+    if (*p) (void)hipHostFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    const size_t n = std::max(need, (size_t)1 << 20);
+    if (hipHostMalloc((void**)p, n, hipHostMallocDefault) != hipSuccess) {
+        *p = nullptr;
+        return false;
+    }
+    *cap = n;
+    return true;
+}
+
+// Byte offsets of the pieces of one request inside its slot's staging.
+struct UpLayout {
+    size_t inst, ids, s0, u, total;
+};
+struct DownLayout {
+    size_t best, simst, bcost, costs, u, traj, A, B, total;
+};
+
+UpLayout up_layout(int C, int T, int ns, int nu) {
+    UpLayout L;
+    size_t o = 0;
+    L.inst = o; o += al(sizeof(InstDev) * C);
+    L.ids = o; o += al(4ull * C);
+    L.s0 = o; o += al(4ull * C * ns);
+    L.u = o; o += al(4ull * C * T * nu);
+    L.total = o;
+    return L;
+}
+
+DownLayout down_layout(int C, int T, int ns, int nu, bool ab) {
+    DownLayout L;
+    size_t o = 0;
+    L.best = o; o += al(4);
+    L.simst = o; o += al(4);
+    L.bcost = o; o += al(4);
+    L.costs = o; o += al(4ull * C);
+    L.u = o; o += al(4ull * T * nu);
+    L.traj = o; o += al(4ull * (T + 1) * ns);
+    L.A = o; o += ab ? al(4ull * T * ns * ns) : 0;
+    L.B = o; o += ab ? al(4ull * T * ns * nu) : 0;
+    L.total = o;
+    return L;
+}
+
 }  // namespace
 
 struct cord_server {
@@ -145,6 +208,7 @@ struct cord_server {
     char* pool = nullptr;
     Arena arena;
     std::vector<hipStream_t> slots;
+    std::vector<Staging> staging;
     std::vector<int> slot_busy;
     std::deque<Req*> queue;
     std::vector<Req*> running;
@@ -212,13 +276,19 @@ bool carve_all(cord_server* s, Req* q) {
     return true;
 }
 
-// Upload and enqueue the whole plan on the request's slot stream.
+// Stage the inputs in the slot's pinned buffer and enqueue, on the slot's
+// stream: uploads, the whole plan, the result download and the completion
+// event.  Returns without waiting for the device.
 bool enqueue(cord_server* s, Req* q) {
     hipStream_t st = s->slots[q->slot];
+    Staging& sg = s->staging[q->slot];
     const int C = q->C, T = q->T, ns = q->ns, nu = q->nu;
     const bool ab = q->r.want_AB != 0;
-    // host staging: candidate table, replicated start state, candidate controls
-    std::vector<InstDev> inst(C);
+    const UpLayout U = up_layout(C, T, ns, nu);
+    const DownLayout D = down_layout(C, T, ns, nu, ab);
+    if (!grow_pinned(&sg.up, &sg.up_cap, U.total) || !grow_pinned(&sg.down, &sg.down_cap, D.total)) return false;
+    // candidate table, replicated start state, candidate controls
+    InstDev* inst = reinterpret_cast<InstDev*>(sg.up + U.inst);
     InstDev base;
     fill_instdev(q->r.inst, base);
     for (int c = 0; c < C; ++c) {
@@ -230,12 +300,13 @@ bool enqueue(cord_server* s, Req* q) {
         inst[c].A_off = 0;
         inst[c].B_off = 0;
     }
-    std::vector<int32_t> ids(C);
+    int32_t* ids = reinterpret_cast<int32_t*>(sg.up + U.ids);
     for (int c = 0; c < C; ++c) ids[c] = c;
-    std::vector<float> s0((size_t)C * ns), u((size_t)C * T * nu);
+    float* s0 = reinterpret_cast<float*>(sg.up + U.s0);
+    float* u = reinterpret_cast<float*>(sg.up + U.u);
     for (int c = 0; c < C; ++c) std::memcpy(&s0[(size_t)c * ns], q->s0.data(), sizeof(float) * ns);
     if (!q->u_init.empty()) {
-        u = q->u_init;
+        std::memcpy(u, q->u_init.data(), sizeof(float) * (size_t)C * T * nu);
     } else {
         uint64_t state = q->r.seed;
         for (int c = 0; c < C; ++c)
@@ -249,11 +320,10 @@ bool enqueue(cord_server* s, Req* q) {
                 u[(size_t)c * T * nu + i] = w + q->r.sigma * z;
             }
     }
-    SRV_HIP(hipMemcpyAsync(q->d_inst, inst.data(), sizeof(InstDev) * C, hipMemcpyHostToDevice, st));
-    SRV_HIP(hipMemcpyAsync(q->d_ids, ids.data(), 4ull * C, hipMemcpyHostToDevice, st));
-    SRV_HIP(hipMemcpyAsync(q->d_s0, s0.data(), 4ull * C * ns, hipMemcpyHostToDevice, st));
-    if (T * nu > 0) SRV_HIP(hipMemcpyAsync(q->d_u, u.data(), 4ull * C * T * nu, hipMemcpyHostToDevice, st));
-    SRV_HIP(hipStreamSynchronize(st));   // staging vectors are pageable and go out of scope
+    SRV_HIP(hipMemcpyAsync(q->d_inst, inst, sizeof(InstDev) * C, hipMemcpyHostToDevice, st));
+    SRV_HIP(hipMemcpyAsync(q->d_ids, ids, 4ull * C, hipMemcpyHostToDevice, st));
+    SRV_HIP(hipMemcpyAsync(q->d_s0, s0, 4ull * C * ns, hipMemcpyHostToDevice, st));
+    if (T * nu > 0) SRV_HIP(hipMemcpyAsync(q->d_u, u, 4ull * C * T * nu, hipMemcpyHostToDevice, st));
 
     int count = 0;
     const KernelCfg* cfg = kernel_configs(&count);
@@ -294,35 +364,45 @@ bool enqueue(cord_server* s, Req* q) {
         l.traj_in = q->d_traj; l.u = q->d_u; l.A = q->d_A; l.Bm = q->d_B;
         l.lin_zero_off = 1;
         l.status = nullptr;
-        SRV_HIP(K.linearize(l, 1, T, st));
+        const int topo = q->r.inst.kind == CORD_ROPE ? kRope : kCloth;
+        SRV_HIP(launch_linearize(q->cfg, topo, bucket_of(topo, q->ns / 6), l, 1, T, st));
+    }
+    // result download into the slot's staging
+    char* h = sg.down;
+    SRV_HIP(hipMemcpyAsync(h + D.best, q->d_best, 4, hipMemcpyDeviceToHost, st));
+    SRV_HIP(hipMemcpyAsync(h + D.simst, q->d_simst, 4, hipMemcpyDeviceToHost, st));
+    SRV_HIP(hipMemcpyAsync(h + D.bcost, q->d_bcost, 4, hipMemcpyDeviceToHost, st));
+    SRV_HIP(hipMemcpyAsync(h + D.costs, q->d_cost, 4ull * C, hipMemcpyDeviceToHost, st));
+    if (T * nu) SRV_HIP(hipMemcpyAsync(h + D.u, q->d_ubest, 4ull * T * nu, hipMemcpyDeviceToHost, st));
+    SRV_HIP(hipMemcpyAsync(h + D.traj, q->d_tbest, 4ull * (T + 1) * ns, hipMemcpyDeviceToHost, st));
+    if (ab) {
+        SRV_HIP(hipMemcpyAsync(h + D.A, q->d_A, 4ull * T * ns * ns, hipMemcpyDeviceToHost, st));
+        if (T * nu) SRV_HIP(hipMemcpyAsync(h + D.B, q->d_B, 4ull * T * ns * nu, hipMemcpyDeviceToHost, st));
     }
     SRV_HIP(hipEventRecord(q->ev, st));
     return true;
 }
 
-bool collect(Req* q) {
+// Copy a finished request's results out of its slot's staging (host only).
+void collect(cord_server* s, Req* q) {
     const int C = q->C, T = q->T, ns = q->ns, nu = q->nu;
-    int32_t best = 0, simst = 0;
-    float bcost = 0.f;
-    SRV_HIP(hipMemcpy(&best, q->d_best, 4, hipMemcpyDeviceToHost));
-    SRV_HIP(hipMemcpy(&simst, q->d_simst, 4, hipMemcpyDeviceToHost));
-    SRV_HIP(hipMemcpy(&bcost, q->d_bcost, 4, hipMemcpyDeviceToHost));
-    q->h_costs.resize(C);
-    SRV_HIP(hipMemcpy(q->h_costs.data(), q->d_cost, 4ull * C, hipMemcpyDeviceToHost));
-    q->h_u.resize((size_t)T * nu);
-    if (T * nu) SRV_HIP(hipMemcpy(q->h_u.data(), q->d_ubest, 4ull * T * nu, hipMemcpyDeviceToHost));
-    q->h_traj.resize((size_t)(T + 1) * ns);
-    SRV_HIP(hipMemcpy(q->h_traj.data(), q->d_tbest, 4ull * (T + 1) * ns, hipMemcpyDeviceToHost));
-    if (q->r.want_AB) {
-        q->h_A.resize((size_t)T * ns * ns);
-        q->h_B.resize((size_t)T * ns * nu);
-        SRV_HIP(hipMemcpy(q->h_A.data(), q->d_A, 4ull * T * ns * ns, hipMemcpyDeviceToHost));
-        if (T * nu) SRV_HIP(hipMemcpy(q->h_B.data(), q->d_B, 4ull * T * ns * nu, hipMemcpyDeviceToHost));
+    const bool ab = q->r.want_AB != 0;
+    const DownLayout D = down_layout(C, T, ns, nu, ab);
+    const char* h = s->staging[q->slot].down;
+    auto take = [&](std::vector<float>& v, size_t off, size_t n) {
+        v.resize(n);
+        if (n) std::memcpy(v.data(), h + off, 4 * n);
+    };
+    take(q->h_costs, D.costs, C);
+    take(q->h_u, D.u, (size_t)T * nu);
+    take(q->h_traj, D.traj, (size_t)(T + 1) * ns);
+    if (ab) {
+        take(q->h_A, D.A, (size_t)T * ns * ns);
+        take(q->h_B, D.B, (size_t)T * ns * nu);
     }
-    q->res.best = best;
-    q->res.sim_status = simst;
-    q->res.cost = bcost;
-    return true;
+    std::memcpy(&q->res.best, h + D.best, 4);
+    std::memcpy(&q->res.sim_status, h + D.simst, 4);
+    std::memcpy(&q->res.cost, h + D.bcost, 4);
 }
 
 void finish(cord_server* s, Req* q, int status) {
@@ -341,24 +421,21 @@ void finish(cord_server* s, Req* q, int status) {
 
 void scheduler(cord_server* s) {
     (void)hipSetDevice(s->device);
+    std::vector<Req*> done, admitted;
     std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
-        bool progressed = false;
-        // completions
+        // completions (the running list and the arena belong to this thread)
+        done.clear();
         for (size_t i = 0; i < s->running.size();) {
             Req* q = s->running[i];
             const hipError_t e = hipEventQuery(q->ev);
             if (e == hipErrorNotReady) { ++i; continue; }
-            int st = e == hipSuccess ? CORD_OK : CORD_EHIP;
-            if (st == CORD_OK && !collect(q)) st = CORD_EHIP;
-            release_blocks(s, q);
-            s->slot_busy[q->slot] = 0;
-            finish(s, q, st);
+            q->res.status = e == hipSuccess ? CORD_OK : CORD_EHIP;
+            done.push_back(q);
             s->running.erase(s->running.begin() + i);
-            progressed = true;
         }
-        if (progressed) s->done_cv.notify_all();
         // admissions: FIFO with bounded skip-ahead
+        admitted.clear();
         if (!s->stop) {
             int scanned = 0;
             for (auto it = s->queue.begin(); it != s->queue.end() && scanned <= kSkipAhead; ++scanned) {
@@ -375,20 +452,42 @@ void scheduler(cord_server* s) {
                 q->state = kRunning;
                 ++s->n_adm;
                 it = s->queue.erase(it);
-                if (!enqueue(s, q)) {
-                    (void)hipStreamSynchronize(s->slots[slot]);
-                    release_blocks(s, q);
-                    s->slot_busy[slot] = 0;
-                    finish(s, q, CORD_EHIP);
-                    s->done_cv.notify_all();
-                    continue;
-                }
-                s->running.push_back(q);
-                progressed = true;
+                admitted.push_back(q);
             }
         }
-        if (s->stop && s->running.empty()) break;
-        if (!progressed) s->cv.wait_for(lk, std::chrono::microseconds(s->running.empty() ? 2000 : 50));
+        if (done.empty() && admitted.empty()) {
+            if (s->stop && s->running.empty()) break;
+            s->cv.wait_for(lk, std::chrono::microseconds(s->running.empty() ? 2000 : 50));
+            continue;
+        }
+        // device and host copies without the lock
+        lk.unlock();
+        for (Req* q : done)
+            if (q->res.status == CORD_OK) collect(s, q);
+        std::vector<int> ok(admitted.size(), 1);
+        for (size_t i = 0; i < admitted.size(); ++i) {
+            if (!enqueue(s, admitted[i])) {
+                (void)hipStreamSynchronize(s->slots[admitted[i]->slot]);
+                ok[i] = 0;
+            }
+        }
+        lk.lock();
+        for (Req* q : done) {
+            release_blocks(s, q);
+            s->slot_busy[q->slot] = 0;
+            finish(s, q, q->res.status);
+        }
+        for (size_t i = 0; i < admitted.size(); ++i) {
+            Req* q = admitted[i];
+            if (ok[i]) {
+                s->running.push_back(q);
+            } else {
+                release_blocks(s, q);
+                s->slot_busy[q->slot] = 0;
+                finish(s, q, CORD_EHIP);
+            }
+        }
+        s->done_cv.notify_all();
     }
 }
 
@@ -415,6 +514,7 @@ int cord_server_create(int32_t device, size_t hbm_budget, int32_t max_slots, int
             return set_error(CORD_EHIP, "stream creation failed");
         }
         s->slots.push_back(st);
+        s->staging.emplace_back();
         s->slot_busy.push_back(0);
     }
     s->th = std::thread(scheduler, s);
@@ -437,6 +537,10 @@ int cord_server_destroy(cord_server* s) {
         delete kv.second;
     }
     for (hipStream_t st : s->slots) (void)hipStreamDestroy(st);
+    for (Staging& g : s->staging) {
+        if (g.up) (void)hipHostFree(g.up);
+        if (g.down) (void)hipHostFree(g.down);
+    }
     if (s->pool) (void)hipFree(s->pool);
     delete s;
     return CORD_OK;

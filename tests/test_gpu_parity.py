@@ -156,7 +156,10 @@ def test_nonfinite_input_flags_only_that_instance():
 def test_linearize_dense(kind):
     import torch
     if kind == "rope":
-        insts = W.small_rope_batch(1, 10, 4, seed=451) + W.small_rope_batch(1, 7, 4, seed=452)
+        # one rope per size class of the direct kernel (32, 64, 128 nodes)
+        # plus a ragged one; T differs so the (instance, step) grid is ragged
+        insts = (W.small_rope_batch(1, 10, 4, seed=451) + W.small_rope_batch(1, 7, 4, seed=452)
+                 + W.small_rope_batch(1, 40, 3, seed=454) + W.small_rope_batch(1, 100, 2, seed=455))
     else:
         insts = W.small_cloth_batch(1, 4, 4, 3, seed=453)
     sim, s0, u, traj, st = _run(insts)
@@ -273,3 +276,63 @@ def test_c1_linearize_in_contact():
               flush=True)
         worst = max(worst, ea, eb)
     assert worst <= JAC_TOL
+
+
+def test_linearize_b_only_and_with_jvp():
+    """B_t alone (no A_t) and A_t together with JVP tangents: the same B_t
+    and the same tangents as the separate calls, within the Jacobian
+    tolerance, and B_t against the oracle."""
+    import torch
+    insts = W.small_rope_batch(1, 24, 3, seed=471) + W.small_rope_batch(1, 50, 3, seed=472)
+    sim, s0, u, traj, st = _run(insts)
+    k = 2
+    rng = np.random.default_rng(9)
+    ds = [rng.normal(size=(i.T, k, i.n_s)) for i in insts]
+    du = [rng.normal(size=(i.T, k, i.n_u)) for i in insts]
+    dst = sim.pack_states([d.ravel() for d in ds])
+    dut = sim.pack_states([d.ravel() for d in du])
+    status = torch.zeros(len(insts), dtype=torch.int32, device=sim.device)
+    A, B1, o1 = sim.linearize(traj, u, jvp_k=k, jvp_ds=dst, jvp_du=dut, status=status)
+    _, B2, _ = sim.linearize(traj, u, dense=False)
+    _, _, o2 = sim.linearize(traj, u, dense=False, want_B=False, jvp_k=k, jvp_ds=dst, jvp_du=dut)
+    torch.cuda.synchronize()
+    assert (status.cpu().numpy() == 0).all()
+    assert torch.equal(o1, o2)
+    b1, b2 = B1.cpu().numpy(), B2.cpu().numpy()
+    assert np.linalg.norm(b1 - b2) <= JAC_TOL * np.linalg.norm(b2)
+    Bp = sim.split(B1, "B")
+    tp = sim.split(traj, "traj")
+    for j, inst in enumerate(insts):
+        tr = tp[j].reshape(inst.T + 1, inst.n_s).astype(np.float64)
+        for t in range(inst.T):
+            _, Br = StepDerivative(inst, tr[t], inst.u[t], inst.kappa_bwd).dense()
+            Bj = Bp[j].reshape(inst.T, inst.n_s, inst.n_u)[t]
+            eb = np.linalg.norm(Bj - Br) / np.linalg.norm(Br)
+            print(f"rope {inst.n} t={t}: B err {eb:.2e}", flush=True)
+            assert eb <= JAC_TOL
+
+
+def test_c2_linearize_full_size_sampled():
+    """Dense A_t/B_t for the full 1024 x 64-node x 100-step rope batch in one
+    launch (60 GB of A_t), sampled (instance, step) blocks against the oracle."""
+    import torch
+    insts = W.config_c2()
+    sim, s0, u, traj, st = _run(insts)
+    status = torch.zeros(len(insts), dtype=torch.int32, device=sim.device)
+    A, Bm, _ = sim.linearize(traj, u, status=status)
+    torch.cuda.synchronize()
+    assert (status.cpu().numpy() == 0).all()
+    offA, offB, offT = sim.offsets()["A"], sim.offsets()["B"], sim.offsets()["traj"]
+    for j, t in [(0, 0), (1, 99), (517, 50), (1023, 7), (700, 93)]:
+        inst = insts[j]
+        ns, nu = inst.n_s, inst.n_u
+        a0 = int(offA[j]) + t * ns * ns
+        b0 = int(offB[j]) + t * ns * nu
+        Aj = A[a0:a0 + ns * ns].cpu().numpy().reshape(ns, ns)
+        Bj = Bm[b0:b0 + ns * nu].cpu().numpy().reshape(ns, nu)
+        tr = traj[int(offT[j]) + t * ns:int(offT[j]) + (t + 1) * ns].cpu().numpy().astype(np.float64)
+        Ar, Br = StepDerivative(inst, tr, inst.u[t], inst.kappa_bwd).dense()
+        ea = np.linalg.norm(Aj - Ar) / np.linalg.norm(Ar)
+        eb = np.linalg.norm(Bj - Br) / np.linalg.norm(Br)
+        print(f"C2 inst {j} t={t}: A err {ea:.2e} B err {eb:.2e}", flush=True)
+        assert ea <= JAC_TOL and eb <= JAC_TOL

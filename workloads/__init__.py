@@ -17,4 +17,5 @@ from .gen import (  # noqa: F401
     small_rope_batch,
     small_cloth_batch,
     random_cotangent,
+    serve_trace,
 )

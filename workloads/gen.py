@@ -256,3 +256,31 @@ def random_cotangent(size: int, seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     w = rng.normal(size=size)
     return w / np.linalg.norm(w)
+
+
+def serve_trace(rate: float = 200.0, duration: float = 60.0, seed: int = 1005, T: int = 30):
+    """Planning requests with Poisson arrivals: a list of
+    (arrival_time_s, Instance, goal_node, goal_point).  Each request is a rope
+    (n ~ U{48..128}) or a cloth (side ~ U{16..32}) with probability 1/2,
+    horizon T, C2/C3-style material, obstacles and warm-start controls; the
+    goal is the last node, steered to a point drawn near its rest position."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    t = 0.0
+    k = 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        sub = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, k])))
+        if sub.random() < 0.5:
+            n = int(sub.integers(48, 129))
+            inst = _c2_instance(sub, n, T)
+        else:
+            side = int(sub.integers(16, 33))
+            inst = _c3_instance(sub, side, side, T)
+        x = inst.s0[:3 * inst.n].reshape(-1, 3)
+        goal = x[-1] + np.array([sub.uniform(-0.1, 0.1), sub.uniform(-0.1, 0.1), sub.uniform(0.0, 0.1)])
+        out.append((t, inst, inst.n - 1, goal))
+        k += 1
+    return out
