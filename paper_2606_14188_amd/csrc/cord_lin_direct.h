@@ -15,10 +15,14 @@
 // ones).  With the increments of the tangent map
 //     eps = -H_ff^{-1} (H_el z)_f,   E = K_ff^{-1} (J_ff eps + Qhat z),
 //     Qhat = (J - K)_ff on free columns, -W_fg on gripped columns,
-// so E never forms dx+ - z by cancellation.  Three sweeps over the rows:
+// so E never forms dx+ - z by cancellation.  Since H_ff eps = -(H_el z)_f,
+// the stage-2 right-hand side needs only G = C - R - W (J = H + G), whose
+// half-bandwidth is 5 (springs reach one particle):
+//     r = G dy - (H_el z)_f - [j free] (N^T Lam N) z,   dy = z + eps.
+// Three sweeps over the rows:
 //   1 (ascending)  w1 = L^{-1} r1         (r1 = -(H_el z)_f is local to j)
-//   2 (descending) eps = L^{-T} w1, r = J eps + Qhat z (lagging 8 rows),
-//                  w2 = U^{-1} r          (U is upper: also descending)
+//   2 (descending) eps = L^{-T} w1, r (lagging 5 rows), w2 = U^{-1} r
+//                  (U is upper triangular: also descending)
 //   3 (ascending)  E = U^{-T} w2, written out as the A_t (and B_t) columns.
 // Choosing U U^T for K makes its first triangular solve run in the same
 // direction as the second solve with L, so one vector per column (w1, then
@@ -37,21 +41,32 @@
 namespace cord {
 
 constexpr int kBand = 8;   // half-bandwidth of H, K, J in scalar unknowns
-constexpr int kRing = 32;  // rows per unrolled block of a sweep (ring size)
-constexpr int kPf = 16;    // rows of prefetch distance for the kept vector
+constexpr int kGB = 5;     // half-bandwidth of G = C - R - W
+constexpr int kRing = 24;  // rows per unrolled block of a sweep (ring size)
+constexpr int kPf = 12;    // rows of prefetch distance for the kept vector
+// Interior blocks of sweep 2 start at a multiple of kRing >= 2 kBand, where
+// every band index they form lies inside the matrix.
+static_assert(kRing >= 2 * kBand && kPf < kRing, "ring too short for the sweep windows");
 
-// LDS carve-up (floats, after the solver's own LDS) for up to 3*NMAX rows.
+// LDS carve-up (floats) for up to 3*NMAX rows.  HB and NL are written only
+// after the assembly has read the solver's LDS mirrors, so they reuse the
+// solver's region (SA floats at the start of the workgroup's LDS); the
+// other bands follow it.
 template <int NMAX>
 struct LinLds {
     static constexpr int N3 = 3 * NMAX;
+    // inside the solver's region
+    static constexpr int HB = 0;                  // H(i, i-m), m = 0..8   [i][9]
+    static constexpr int NL = HB + N3 * 9;        // (w n n^T) row i, same-particle columns [i][3]
+    static constexpr int SA = NL + N3 * 3;
+    // after the solver's region
     static constexpr int LC = 0;                  // L(k+m, k), m = 1..8   [k][8]
     static constexpr int LI = LC + N3 * 8;        // 1 / L(k, k)
     static constexpr int UW = LI + N3;            // U(i-m, i) at [N-1-i][m-1]
     static constexpr int UD = UW + N3 * 8;        // 1 / U(i, i) at [N-1-i]
-    static constexpr int HB = UD + N3;            // H(i, i-m), m = 0..8   [i][9]
-    static constexpr int JB = HB + N3 * 9;        // J(i, i-8+q), q = 0..16 [i][20]
-    static constexpr int NL = JB + N3 * 20;       // (w n n^T) row i, same-particle columns [i][3]
-    static constexpr int RF = NL + N3 * 3;        // 1 if row i is free
+    static constexpr int UR = UD + N3;            // U(i, i+m), m = 1..8   [i][8]
+    static constexpr int GB = UR + N3 * 8;        // G(i, i-5+q), q = 0..10 [i][12]
+    static constexpr int RF = GB + N3 * 12;       // 1 if row i is free
     static constexpr int TOTAL = RF + N3;
 };
 
@@ -63,11 +78,14 @@ __device__ __forceinline__ void sym_to_full(const float s[6], float m[3][3]) {
 
 // Banded Cholesky (half-bandwidth 8) by one wavefront, in place:
 // C[k][m-1] = A(k+m, k) -> L(k+m, k),  Dg[k] = A(k, k) -> 1 / L(k, k).
-// Right-looking: step k scales column k (lanes 1..8) and updates the 36
-// entries of the trailing 8x8 window (one lane each).  Steps depend on each
-// other only through LDS, whose reads and writes a wavefront performs in
-// program order.  Returns false if a pivot was not positive (it is then
-// replaced by 1 so that the sweeps stay finite).
+// Right-looking: step k scales column k (lanes 1..8) and applies the rank-1
+// update to the 36 entries of the trailing 8x8 window (one lane each).  All
+// LDS reads of a step are issued together before any of its writes (the
+// entries a step updates are not read again within the step), so a step
+// costs one LDS round trip; steps depend on each other only through LDS,
+// whose reads and writes a wavefront performs in program order.  Rows past
+// N act as identity rows.  Returns false if a pivot was not positive (it is
+// then replaced by 1 so that the sweeps stay finite).
 __device__ __forceinline__ bool band_cholesky(float* C, float* Dg, int N) {
     const int lane = (int)threadIdx.x & 63;
     // lanes 0..35 -> (a, b), 1 <= a <= b <= 8, column-major over b
@@ -80,31 +98,31 @@ __device__ __forceinline__ bool band_cholesky(float* C, float* Dg, int N) {
     }
     const bool upd = lane < 36;
     const bool scl = lane >= 1 && lane <= kBand;
+    // update target of this lane, relative to step k: Dg[k + a] or C[k + a][b - a - 1]
+    float* const tgt0 = (ua == ub) ? Dg + ua : C + ua * 8 + (ub - ua) - 1;
+    const int tstride = (ua == ub) ? 1 : 8;
+    const int ca = upd ? ua - 1 : 0, cb = upd ? ub - 1 : 0, cm = scl ? lane - 1 : 0;
     bool ok = true;
     for (int k = 0; k < N; ++k) {
+        const bool live = upd && k + ub < N;
+        float* const tgt = tgt0 + k * tstride;
         float d = Dg[k];
-        if (!(d > 0.f)) { ok = false; d = 1.f; }
-        const float is = 1.0f / sqrtf(d);
-        float la = 0.f, lb = 0.f, lm = 0.f;
-        if (upd && k + ub < N) {
-            la = C[k * 8 + ua - 1] * is;
-            lb = C[k * 8 + ub - 1] * is;
-        }
-        if (scl && k + lane < N) lm = C[k * 8 + lane - 1] * is;
+        const float xa = C[k * 8 + ca], xb = C[k * 8 + cb], xm = C[k * 8 + cm];
+        const float tv = live ? *tgt : 0.f;
         __builtin_amdgcn_wave_barrier();
-        if (scl) C[k * 8 + lane - 1] = lm;
+        ok = ok && (d > 0.f);
+        d = d > 0.f ? d : 1.f;
+        const float is = 1.0f / sqrtf(d);
+        if (scl) C[k * 8 + lane - 1] = (k + lane < N) ? xm * is : 0.f;
         if (lane == 0) Dg[k] = is;
-        if (upd && k + ub < N) {
-            if (ua == ub) Dg[k + ua] -= la * la;
-            else C[(k + ua) * 8 + (ub - ua) - 1] -= la * lb;
-        }
+        if (live) *tgt = tv - (xa * is) * (xb * is);
         __builtin_amdgcn_wave_barrier();
     }
     return ok;
 }
 
 template <int NT, int NMAX, int NOBS>
-__global__ __launch_bounds__(NT) void linearize_direct_kernel(KArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void linearize_direct_kernel(KArgs a) {
     static_assert(NT % 64 == 0 && NT >= 3 * NMAX && NT >= 128, "one lane per column, two factor waves");
     using LL = LinLds<NMAX>;
     extern __shared__ float lds[];
@@ -124,9 +142,11 @@ __global__ __launch_bounds__(NT) void linearize_direct_kernel(KArgs a) {
     float* LI = B + LL::LI;
     float* UW = B + LL::UW;
     float* UD = B + LL::UD;
-    float* HB = B + LL::HB;
-    float* JB = B + LL::JB;
-    float* NL = B + LL::NL;
+    static_assert(LL::SA <= lds_floats<NT, 1>(), "HB and NL must fit in the solver's LDS");
+    float* HB = lds + LL::HB;
+    float* UR = B + LL::UR;
+    float* GB = B + LL::GB;
+    float* NL = lds + LL::NL;
     float* RF = B + LL::RF;
 
     // ---------------------------------------------------------- assembly
@@ -203,6 +223,9 @@ __global__ __launch_bounds__(NT) void linearize_direct_kernel(KArgs a) {
                 }
             }
         }
+        // the solver's LDS mirrors are read for the last time above; HB and
+        // NL are written over them below
+        __syncthreads();
         // bending: particle c in [1, n-2] carries the stencil (1, -2, 1)
         const float kb = S.kb;
         auto inR = [&](int c) { return (c >= 1 && c <= n - 2) ? 1.f : 0.f; };
@@ -289,18 +312,17 @@ __global__ __launch_bounds__(NT) void linearize_direct_kernel(KArgs a) {
                         UW[(N - 1 - i) * 8 + m - 1] = kf;
                     }
                 }
-                // J row (free rows; zero on gripped rows)
+                // G row (free rows; zero on gripped rows)
 #pragma unroll
-                for (int qq = 0; qq <= 2 * kBand; ++qq) {
-                    const int k = i - kBand + qq;
-                    const int off = r - kBand + qq;
+                for (int qq = 0; qq < 12; ++qq) {
+                    const int k = i - kGB + qq;
+                    const int off = r - kGB + qq;
                     const int dq = off >= 0 ? off / 3 : -((2 - off) / 3);
                     const int c = off - 3 * dq;
-                    float jv = 0.f;
-                    if (fr && k >= 0 && k < N) {
-                        jv = Hblk(dq, r, c) - Wblk(dq, r, c) + (dq == 0 ? Cp[r][c] - Rp[r][c] : 0.f);
-                    }
-                    JB[i * 20 + qq] = jv;
+                    float gv = 0.f;
+                    if (qq <= 2 * kGB && fr && k >= 0 && k < N)
+                        gv = -Wblk(dq, r, c) + (dq == 0 ? Cp[r][c] - Rp[r][c] : 0.f);
+                    GB[i * 12 + qq] = gv;
                 }
             }
         }
@@ -321,12 +343,18 @@ __global__ __launch_bounds__(NT) void linearize_direct_kernel(KArgs a) {
     __syncthreads();
     // ---------------------------------------------------------- factorizations
     {
+        // wavefront 0 factors H_ff, wavefront 1 the reversed K_ff
         const int wv = threadIdx.x >> 6;
         bool ok = true;
         if (wv == 0) ok = band_cholesky(LC, LI, N);
         else if (wv == 1) ok = band_cholesky(UW, UD, N);
         if (!ok && (threadIdx.x & 63) == 0 && a.status) atomicMax(&a.status[id], kStNotPD);
     }
+    __syncthreads();
+    // row layout of U for the descending solve: UR[i][m-1] = U(i, i+m)
+    for (int i = threadIdx.x; i < N; i += NT)
+#pragma unroll
+        for (int m = 1; m <= kBand; ++m) UR[i * 8 + m - 1] = i + m < N ? UW[(N - 1 - i - m) * 8 + m - 1] : 0.f;
     __syncthreads();
 
     // ---------------------------------------------------------- column sweeps
@@ -344,90 +372,110 @@ __global__ __launch_bounds__(NT) void linearize_direct_kernel(KArgs a) {
             if (I.grip_node[g] == pj) gj = g;
         const int i0 = max(0, (int)(threadIdx.x & ~63) - kBand);
 
-        // sweep 1: w1 = L^{-1} r1, rows i0..N-1
+        // Each sweep runs in blocks of kRing rows whose body is unrolled, so
+        // the ring slot of a row (its position mod kRing) is a constant and
+        // the rolling windows stay in registers.  Blocks that cannot reach
+        // past either end of the matrix run a body without any condition
+        // (one basic block: the LDS band reads of all its rows can be issued
+        // ahead of the arithmetic); the first and last blocks run the
+        // guarded body.  Sums are taken from the oldest window entry to the
+        // newest, so each recurrence waits on one multiply-add per row.
+        const float lane_fj = fj ? 1.f : 0.f;
+
+        // sweep 1: w1 = L^{-1} r1 for rows i0..N-1 (rows above i0 are zero
+        // for every column of this wavefront and are stored as zeros)
+        for (int i = 0; i < i0; ++i) Sv[(int64_t)i * ns] = 0.f;
         {
             float w[kRing];
 #pragma unroll
             for (int u = 0; u < kRing; ++u) w[u] = 0.f;
+            auto row = [&](const int i, const int u, const bool guard) {
+                if (guard && i >= N) return;
+                const int dd = i - j;
+                const int ddc = min(max(dd, -kBand), kBand);
+                const float h = HB[ddc >= 0 ? i * 9 + ddc : j * 9 - ddc];
+                const float in = (dd == ddc) ? RF[i] : 0.f;
+                float acc = -in * (h - (dd == 0 ? mdt2 : 0.f));
+#pragma unroll
+                for (int m = kBand; m >= 1; --m)
+                    if (!guard || i - m >= i0) acc -= LC[(i - m) * 8 + m - 1] * w[(u - m + kRing) % kRing];
+                const float wi = acc * LI[i];
+                w[u] = wi;
+                Sv[(int64_t)i * ns] = wi;
+            };
             for (int tb = 0; i0 + tb < N; tb += kRing) {
+                const bool plain = tb > 0 && i0 + tb + kRing <= N;
+                if (plain) {
 #pragma unroll
-                for (int u = 0; u < kRing; ++u) {
-                    const int i = i0 + tb + u;
-                    if (i < N) {
-                        const int dd = i - j;
-                        float r1 = 0.f;
-                        if (dd >= -kBand && dd <= kBand && RF[i] != 0.f) {
-                            const float h = dd >= 0 ? HB[i * 9 + dd] : HB[j * 9 - dd];
-                            r1 = -(h - (dd == 0 ? mdt2 : 0.f));
-                        }
-                        float acc = r1;
+                    for (int u = 0; u < kRing; ++u) row(i0 + tb + u, u, false);
+                } else {
 #pragma unroll
-                        for (int m = 1; m <= kBand; ++m)
-                            if (i - m >= i0) acc -= LC[(i - m) * 8 + m - 1] * w[(u - m + kRing) % kRing];
-                        const float wi = acc * LI[i];
-                        w[u] = wi;
-                        Sv[(int64_t)i * ns] = wi;
-                    }
+                    for (int u = 0; u < kRing; ++u) row(i0 + tb + u, u, true);
                 }
             }
         }
-        // sweep 2 (descending, position s = N-1-i): eps, r (8 rows behind), w2
+        // sweep 2 (descending, position s = N-1-i): eps, r (kGB rows behind), w2
         {
             float e[kRing], w2[kRing], pf[kRing];
 #pragma unroll
             for (int u = 0; u < kRing; ++u) { e[u] = 0.f; w2[u] = 0.f; pf[u] = 0.f; }
 #pragma unroll
-            for (int u = 0; u < kPf; ++u) {
-                const int i = N - 1 - u;
-                pf[u] = (i >= i0) ? Sv[(int64_t)i * ns] : 0.f;
-            }
-            for (int sb = 0; sb < N + kBand; sb += kRing) {
+            for (int u = 0; u < kPf; ++u) pf[u] = Sv[(int64_t)max(N - 1 - u, 0) * ns];
+            auto row = [&](const int sp, const int u, const bool guard) {
+                const int i = N - 1 - sp;
+                if (guard && sp >= N + kGB) return;
+                // prefetch the kept value kPf rows ahead (a clamped row is
+                // loaded but never used)
+                pf[(u + kPf) % kRing] = Sv[(int64_t)max(i - kPf, 0) * ns];
+                float ei = 0.f;
+                if (!guard || i >= 0) {
+                    const float4 l0 = *reinterpret_cast<const float4*>(LC + i * 8);
+                    const float4 l1 = *reinterpret_cast<const float4*>(LC + i * 8 + 4);
+                    const float lc[8] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
+                    float acc = pf[u];
 #pragma unroll
-                for (int u = 0; u < kRing; ++u) {
-                    const int s = sb + u;
-                    const int i = N - 1 - s;
-                    if (s < N + kBand) {
-                        // prefetch the kept value kPf rows ahead
-                        {
-                            const int ip = i - kPf;
-                            if (ip >= i0) pf[(u + kPf) % kRing] = Sv[(int64_t)ip * ns];
-                        }
-                        float ei = 0.f;
-                        if (i >= 0) {
-                            float acc = (i >= i0) ? pf[u] : 0.f;
+                    for (int m = kBand; m >= 1; --m) acc -= lc[m - 1] * e[(u - m + kRing) % kRing];
+                    ei = acc * LI[i];
+                }
+                e[u] = ei;
+                const int mrow = i + kGB;
+                if (guard && mrow >= N) { w2[u] = 0.f; return; }
+                // column-local part: G(m, j) - (H(m, j) - mdt2 d_mj) - [j free, same particle] NLN(m, j)
+                const int dq = j - mrow;
+                const int dqc = min(max(dq, -kBand), kBand), dgc = min(max(dq, -kGB), kGB);
+                const float hv = HB[dqc <= 0 ? mrow * 9 - dqc : j * 9 + dqc];
+                const float gv = GB[mrow * 12 + kGB + dgc];
+                const float same = ((mrow / 3) == pj) ? lane_fj : 0.f;
+                const float nv = NL[mrow * 3 + cj] * same;
+                const float in8 = (dq == dqc) ? 1.f : 0.f, in5 = (dq == dgc) ? 1.f : 0.f;
+                float r = in8 * (in5 * gv - nv - (hv - (dq == 0 ? mdt2 : 0.f)));
+                // G(m, m-5..m+5) eps; e[(u - qq)] holds eps_{mrow - 5 + qq}
+                const float4 g0 = *reinterpret_cast<const float4*>(GB + mrow * 12);
+                const float4 g1 = *reinterpret_cast<const float4*>(GB + mrow * 12 + 4);
+                const float4 g2 = *reinterpret_cast<const float4*>(GB + mrow * 12 + 8);
+                const float gr[12] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w, g2.x, g2.y, g2.z, g2.w};
 #pragma unroll
-                            for (int m = 1; m <= kBand; ++m) acc -= LC[i * 8 + m - 1] * e[(u - m + kRing) % kRing];
-                            ei = acc * LI[i];
-                        }
-                        e[u] = ei;
-                        const int mrow = i + kBand;
-                        if (mrow < N) {
-                            float r = 0.f;
-                            if (RF[mrow] != 0.f) {
-                                // e[(u - 16 + qq)] holds eps_{mrow - 8 + qq}
+                for (int qq = 2 * kGB; qq >= 0; --qq) r += gr[qq] * e[(u - qq + kRing) % kRing];
+                r *= RF[mrow];
+                const float4 q0 = *reinterpret_cast<const float4*>(UR + mrow * 8);
+                const float4 q1 = *reinterpret_cast<const float4*>(UR + mrow * 8 + 4);
+                const float ur[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+                float pre = 0.f;
 #pragma unroll
-                                for (int qq = 0; qq <= 2 * kBand; ++qq)
-                                    r += JB[mrow * 20 + qq] * e[(u - qq + kRing) % kRing];
-                                const int dq = j - mrow;
-                                if (dq >= -kBand && dq <= kBand) {
-                                    const float jv = JB[mrow * 20 + kBand + dq];
-                                    const float hv = dq <= 0 ? HB[mrow * 9 - dq] : HB[j * 9 + dq];
-                                    const bool same = (mrow / 3) == pj;
-                                    const float nv = (same && fj) ? NL[mrow * 3 + cj] : 0.f;
-                                    r += jv - hv - nv;
-                                }
-                            }
-                            float acc = r;
+                for (int q = kBand; q >= 2; --q) pre += ur[q - 1] * w2[(u - q + kRing) % kRing];
+                const float acc = (r - pre) - ur[0] * w2[(u - 1 + kRing) % kRing];
+                const float wv = acc * UD[N - 1 - mrow];
+                w2[u] = wv;
+                Sv[(int64_t)mrow * ns] = wv;
+            };
+            for (int sb = 0; sb < N + kGB; sb += kRing) {
+                const bool plain = sb >= kGB && sb + kRing <= N;
+                if (plain) {
 #pragma unroll
-                            for (int q = 1; q <= kBand; ++q)
-                                if (mrow + q < N) acc -= UW[(N - 1 - mrow - q) * 8 + q - 1] * w2[(u - q + kRing) % kRing];
-                            const float wv = acc * UD[N - 1 - mrow];
-                            w2[u] = wv;
-                            Sv[(int64_t)mrow * ns] = wv;
-                        } else {
-                            w2[u] = 0.f;
-                        }
-                    }
+                    for (int u = 0; u < kRing; ++u) row(sb + u, u, false);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < kRing; ++u) row(sb + u, u, true);
                 }
             }
         }
@@ -437,39 +485,37 @@ __global__ __launch_bounds__(NT) void linearize_direct_kernel(KArgs a) {
 #pragma unroll
             for (int u = 0; u < kRing; ++u) { E[u] = 0.f; pf[u] = 0.f; }
 #pragma unroll
-            for (int u = 0; u < kPf; ++u)
-                if (u < N) pf[u] = Sv[(int64_t)u * ns];
+            for (int u = 0; u < kPf; ++u) pf[u] = Sv[(int64_t)min(u, N - 1) * ns];
             const float c1 = dt * (1.f - gam), omg = 1.f - gam;
+            const float cv = fj ? c1 : 0.f, vv = fj ? omg : 0.f;
+            auto row = [&](const int i, const int u, const bool guard) {
+                if (guard && i >= N) return;
+                pf[(u + kPf) % kRing] = Sv[(int64_t)min(i + kPf, N - 1) * ns];
+                const float4 c0 = *reinterpret_cast<const float4*>(UW + (N - 1 - i) * 8);
+                const float4 c1v = *reinterpret_cast<const float4*>(UW + (N - 1 - i) * 8 + 4);
+                const float uc[8] = {c0.x, c0.y, c0.z, c0.w, c1v.x, c1v.y, c1v.z, c1v.w};
+                float acc = pf[u];
+#pragma unroll
+                for (int q = kBand; q >= 1; --q) acc -= uc[q - 1] * E[(u - q + kRing) % kRing];
+                const float Ei = acc * UD[N - 1 - i];
+                E[u] = Ei;
+                const float dx = (i == j ? 1.f : 0.f) + Ei;
+                At[(int64_t)i * ns + j] = dx;
+                At[(int64_t)(N + i) * ns + j] = Ei * idt;
+                At[(int64_t)i * ns + N + j] = cv * dx;
+                At[(int64_t)(N + i) * ns + N + j] = vv * dx;
+                if (Bt && gj >= 0) {
+                    Bt[(int64_t)i * nu + 3 * gj + cj] = dt * dx;
+                    Bt[(int64_t)(N + i) * nu + 3 * gj + cj] = dx;
+                }
+            };
             for (int tb = 0; tb < N; tb += kRing) {
+                if (tb + kRing <= N) {
 #pragma unroll
-                for (int u = 0; u < kRing; ++u) {
-                    const int i = tb + u;
-                    if (i < N) {
-                        {
-                            const int ip = i + kPf;
-                            if (ip < N) pf[(u + kPf) % kRing] = Sv[(int64_t)ip * ns];
-                        }
-                        float acc = pf[u];
+                    for (int u = 0; u < kRing; ++u) row(tb + u, u, false);
+                } else {
 #pragma unroll
-                        for (int q = 1; q <= kBand; ++q)
-                            acc -= UW[(N - 1 - i) * 8 + q - 1] * E[(u - q + kRing) % kRing];
-                        const float Ei = acc * UD[N - 1 - i];
-                        E[u] = Ei;
-                        const float dx = (i == j ? 1.f : 0.f) + Ei;
-                        At[(int64_t)i * ns + j] = dx;
-                        At[(int64_t)(N + i) * ns + j] = Ei * idt;
-                        if (fj) {
-                            At[(int64_t)i * ns + N + j] = c1 * dx;
-                            At[(int64_t)(N + i) * ns + N + j] = omg * dx;
-                        } else {
-                            At[(int64_t)i * ns + N + j] = 0.f;
-                            At[(int64_t)(N + i) * ns + N + j] = 0.f;
-                            if (Bt && gj >= 0) {
-                                Bt[(int64_t)i * nu + 3 * gj + cj] = dt * dx;
-                                Bt[(int64_t)(N + i) * nu + 3 * gj + cj] = dx;
-                            }
-                        }
-                    }
+                    for (int u = 0; u < kRing; ++u) row(tb + u, u, true);
                 }
             }
         }
