@@ -165,10 +165,49 @@ def bench_c4(args):
         def step():
             sim.rollout(s0, u, out=traj)
             sim.backward(u, traj, sT_bar=sT)
-        tms = _time(step, 1, max(1, args.steps // 2))
+        # one launch per instance is the slow baseline: one untimed-warmup-free pass
+        tms = _time(step, 0, 1) if mode == L.LAUNCH_PER_INSTANCE else _time(step, 1, max(1, args.steps // 2))
         out[name] = {"ms_per_step": tms, "particle_steps_per_s": ps / (tms / 1e3)}
         print(name, out[name], file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
+
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PROFILE = os.path.join(HERE, "profiles", "rollout_backward_linearize__rope64x1024_T100.md")
+LIN_SOURCES = ["cord_lin_direct.h", "cord_solver.h", "cord_lin_rope.hip"]
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None if there is none for it or the
+    kernel's sources have changed since the counters were taken."""
+    import hashlib
+    import re
+    if kernel != "linearize" or not os.path.exists(PROFILE):
+        return None
+    m = re.search(r"traffic: kernel=linearize bytes_per_launch=(\d+) sources_sha1=([0-9a-f]{40})",
+                  open(PROFILE).read())
+    if not m:
+        return None
+    h = hashlib.sha1()
+    for f in LIN_SOURCES:
+        with open(os.path.join(HERE, "paper_2606_14188_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return int(m.group(1)) if h.hexdigest() == m.group(2) else None
+
+
+def copy_calibration():
+    """Plain device copy of 256 MiB, three times: the reference dispatch that
+    scales the FETCH_SIZE / WRITE_SIZE counters of a profile to bytes."""
+    import torch
+    n = 256 * 1024 * 1024 // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "copy calibration", "bytes_per_copy": n * 4, "copies": 3}), flush=True)
 
 
 def bench_probe(args):
@@ -283,7 +322,7 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=8)
     ap.add_argument("--cpu-per-worker", type=int, default=1)
     ap.add_argument("--cpu-T", type=int, default=25)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "probe"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "probe", "copy"])
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--no-serve", action="store_true", help="skip the short planning-stream leg")
@@ -297,6 +336,8 @@ def main():
         return bench_c3(args)
     if args.workload == "c4":
         return bench_c4(args)
+    if args.workload == "copy":
+        return copy_calibration()
     if args.workload == "probe":
         return bench_probe(args)
     if args.workload == "c5":
@@ -391,7 +432,7 @@ def main():
     dom = max(kernels, key=lambda k: kern_ms[k])
     roof = dict(kernels[dom])
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = profiled_traffic(dom)
     roof["kernel"] = dom
     serve = None
     if not args.no_serve:
