@@ -22,6 +22,13 @@ targets, H = dF/dy at y*, which is also the stage-2 matrix P):
            dxhat = dx + dt (1 - gamma) dv,   db = dx_g + dt du
   output:  dv+_f = (dx+_f - dx_f)/dt,  dx+_g = db,  dv+_g = du.
 
+Penalty grasp (all nodes free, gripper state g, g+ = g + dt u, stiffness
+D_k(c_k), c_k = x_j - g_k): F gains D_k (y_j - g+_k), so dF/dtheta gains
+(y_j - g+_k) dD_k - D_k dg+_k at node j, and P gains D_k I, so the stage-2
+right-hand side gains -(dD_k) Delta_j at node j:
+  H dy = (M/dt^2) dxhat - sum_k e_j [dD_k (y_j - g+_k) - D_k dg+_k]
+  K dx+ = J dy - sum_k e_j dD_k Delta_j,   dD_k = D'_k . (dx_j - dg_k)
+
 Every product above is a plain sparse matrix product; every inverse is a
 sparse LU solve.
 """
@@ -32,7 +39,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from . import model
-from .step import Layout, normal_matrix, psi_hessian_ff, rollout, step
+from .step import Layout, normal_matrix, psi_hessian_ff, rollout, split_state, step
 
 
 def _blockdiag(lay, pair_node, mats):
@@ -56,15 +63,14 @@ class StepDerivative:
         self.lay = Layout(inst) if lay is None else lay
         n = inst.n
         self.n = n
-        s = np.asarray(s, dtype=np.float64)
-        self.x = s[:3 * n].reshape(n, 3)
-        self.v = s[3 * n:].reshape(n, 3)
-        self.res = r = step(inst, self.x, self.v, u_t, kappa, self.el, self.lay)
+        self.x, self.v, self.g = split_state(inst, s)
+        self.res = r = step(inst, self.x, self.v, u_t, kappa, self.el, self.lay, g=self.g)
+        self.pen = r.pen
         self.kappa = kappa
         lay = self.lay
         fi, gi = lay.fidx, lay.gidx
         Hfull = model.hessian(self.el, r.y)
-        self.Hff = psi_hessian_ff(inst, self.el, lay, r.y, project=False)
+        self.Hff = psi_hessian_ff(inst, self.el, lay, r.y, project=False, pen=r.pen)
         self.Hfg = Hfull[fi][:, gi].tocsr()
         Wfull = model.third(self.el, r.y, r.delta)
         self.Wff = Wfull[fi][:, fi].tocsr()
@@ -94,8 +100,9 @@ class StepDerivative:
             self.nA = na
 
     # ------------------------------------------------------------------ JVP
-    def jvp(self, dx, dv, du):
-        """Tangents (3n, m), (3n, m), (n_u, m) -> (dx+, dv+), each (3n, m)."""
+    def jvp(self, dx, dv, du, dg=None):
+        """Tangents (3n, m), (3n, m), (n_u, m) [, (3 n_g, m) in penalty mode]
+        -> (dx+, dv+), each (3n, m) [, dg+ in penalty mode]."""
         inst, lay = self.inst, self.lay
         dt, gam = inst.dt, inst.gamma
         dx = np.asarray(dx, dtype=np.float64)
@@ -105,16 +112,27 @@ class StepDerivative:
             dx, dv, du = dx[:, None], dv[:, None], du[:, None]
         m = dx.shape[1]
         db = np.zeros_like(dx)
-        for k, j in enumerate(inst.grip_nodes):
-            db[3 * j:3 * j + 3] = dx[3 * j:3 * j + 3] + dt * du[3 * k:3 * k + 3]
+        if self.pen is None:
+            for k, j in enumerate(inst.grip_nodes):
+                db[3 * j:3 * j + 3] = dx[3 * j:3 * j + 3] + dt * du[3 * k:3 * k + 3]
         fi, gi = lay.fidx, lay.gidx
         dxhat_f = dx[fi] + dt * (1.0 - gam) * dv[fi]
         rhs1 = inst.mass / dt ** 2 * dxhat_f - self.Hfg @ db[gi]
+        pen2 = np.zeros_like(rhs1)
+        if self.pen is not None:
+            dg = np.zeros((3 * len(inst.grip_nodes), m)) if dg is None else np.asarray(dg, dtype=np.float64).reshape(-1, m)
+            r, P = self.res, self.pen
+            for k, j in enumerate(P.nodes):
+                sl = slice(3 * j, 3 * j + 3)
+                dgp = dg[3 * k:3 * k + 3] + dt * du[3 * k:3 * k + 3]
+                dDk = P.dD[k] @ (dx[sl] - dg[3 * k:3 * k + 3])            # (m,)
+                rhs1[sl] -= np.outer(r.y[j] - P.gplus[k], dDk) - P.D[k] * dgp
+                pen2[sl] -= np.outer(r.delta[j], dDk)
         dy_f = self.Hlu.solve(rhs1)
         if self.kappa > 0.0:
-            dxn_f = self.Klu.solve(self.J @ dy_f - self.Wfg @ db[gi])
+            dxn_f = self.Klu.solve(self.J @ dy_f - self.Wfg @ db[gi] + pen2)
         else:
-            top = -((self.Wff - self.C) @ dy_f + self.Wfg @ db[gi])
+            top = -((self.Wff - self.C) @ dy_f + self.Wfg @ db[gi]) + pen2
             bot = -((self.NA + self.RA) @ dy_f) if self.nA else np.zeros((0, m))
             sol = np.linalg.solve(self.Kkkt, np.vstack([top, bot])) if self.nA else \
                 np.linalg.solve(self.Kkkt, top)
@@ -122,13 +140,16 @@ class StepDerivative:
         dxn = db.copy()
         dxn[fi] = dxn_f
         dvn = (dxn - dx) / dt
+        if self.pen is not None:
+            return dxn, dvn, dg + dt * du
         for k, j in enumerate(inst.grip_nodes):
             dvn[3 * j:3 * j + 3] = du[3 * k:3 * k + 3]
         return dxn, dvn
 
     # ------------------------------------------------------------------ VJP
-    def vjp(self, xb, vb):
-        """Cotangents of (x+, v+) (3n,) -> cotangents of (x, v, u)."""
+    def vjp(self, xb, vb, gb=None):
+        """Cotangents of (x+, v+) (3n,) [and g+ in penalty mode] -> cotangents
+        of (x, v, u) [(x, v, g, u) in penalty mode]."""
         inst, lay = self.inst, self.lay
         dt, gam = inst.dt, inst.gamma
         fi, gi = lay.fidx, lay.gidx
@@ -142,13 +163,15 @@ class StepDerivative:
         xbar[fi] -= vb[fi] / dt
         bbar = np.zeros(3 * self.n)
         bbar[gi] = xb[gi]
-        for k, j in enumerate(inst.grip_nodes):
-            ubar[3 * k:3 * k + 3] += vb[3 * j:3 * j + 3]
+        if self.pen is None:
+            for k, j in enumerate(inst.grip_nodes):
+                ubar[3 * k:3 * k + 3] += vb[3 * j:3 * j + 3]
         # stage 2
         if self.kappa > 0.0:
             z = self.Klu.solve(xnb_f)
             ybar_f = self.J.T @ z
             bbar[gi] -= self.Wfg.T @ z
+            a2 = z
         else:
             nf = len(fi)
             rhs = np.concatenate([xnb_f, np.zeros(self.nA)])
@@ -158,29 +181,56 @@ class StepDerivative:
             if self.nA:
                 ybar_f = ybar_f - (self.NA + self.RA).T @ c
             bbar[gi] -= self.Wfg.T @ a
+            a2 = a
         # stage 1
         mu = self.Hlu.solve(ybar_f)
         xhatb_f = inst.mass / dt ** 2 * mu
         bbar[gi] -= self.Hfg.T @ mu
         xbar[fi] += xhatb_f
         vbar[fi] += dt * (1.0 - gam) * xhatb_f
+        if self.pen is not None:
+            r, P = self.res, self.pen
+            ng = len(inst.grip_nodes)
+            gbar = np.zeros(3 * ng) if gb is None else np.array(gb, dtype=np.float64)
+            for k, j in enumerate(P.nodes):
+                sl = slice(3 * j, 3 * j + 3)
+                Dbar = -(a2[sl] @ r.delta[j]) - (mu[sl] @ (r.y[j] - P.gplus[k]))
+                gpbar = P.D[k] * mu[sl] + gbar[3 * k:3 * k + 3]
+                xbar[sl] += Dbar * P.dD[k]
+                gbar[3 * k:3 * k + 3] = gpbar - Dbar * P.dD[k]
+                ubar[3 * k:3 * k + 3] = dt * gpbar
+            return xbar, vbar, gbar, ubar
         for k, j in enumerate(inst.grip_nodes):
             xbar[3 * j:3 * j + 3] += bbar[3 * j:3 * j + 3]
             ubar[3 * k:3 * k + 3] += dt * bbar[3 * j:3 * j + 3]
         return xbar, vbar, ubar
 
+    # ------------------------------------------------------ full-state forms
+    def jvp_s(self, ds, du):
+        """ds (n_s, m), du (n_u, m) -> ds+ (n_s, m), for either grasp mode."""
+        n = self.n
+        ds = np.asarray(ds, dtype=np.float64)
+        if self.pen is None:
+            return np.vstack(self.jvp(ds[:3 * n], ds[3 * n:6 * n], du))
+        return np.vstack(self.jvp(ds[:3 * n], ds[3 * n:6 * n], du, ds[6 * n:]))
+
+    def vjp_s(self, sb):
+        """sb (n_s,) -> (cotangent of s (n_s,), cotangent of u (n_u,))."""
+        n = self.n
+        sb = np.asarray(sb, dtype=np.float64)
+        if self.pen is None:
+            xb, vb, ub = self.vjp(sb[:3 * n], sb[3 * n:6 * n])
+            return np.concatenate([xb, vb]), ub
+        xb, vb, gb, ub = self.vjp(sb[:3 * n], sb[3 * n:6 * n], sb[6 * n:])
+        return np.concatenate([xb, vb, gb]), ub
+
     # ---------------------------------------------------------------- dense
     def dense(self):
-        """A = ds+/ds (6n x 6n), B = ds+/du (6n x n_u)."""
-        n3 = 3 * self.n
+        """A = ds+/ds (n_s x n_s), B = ds+/du (n_s x n_u)."""
+        ns = self.inst.n_s
         nu = 3 * len(self.inst.grip_nodes)
-        I = np.eye(n3)
-        Z = np.zeros((n3, n3))
-        ax, av = self.jvp(I, Z, np.zeros((nu, n3)))
-        bx, bv = self.jvp(Z, I, np.zeros((nu, n3)))
-        cx, cv = self.jvp(np.zeros((n3, nu)), np.zeros((n3, nu)), np.eye(nu))
-        A = np.block([[ax, bx], [av, bv]])
-        B = np.vstack([cx, cv])
+        A = self.jvp_s(np.eye(ns), np.zeros((nu, ns)))
+        B = self.jvp_s(np.zeros((ns, nu)), np.eye(nu))
         return A, B
 
 
@@ -191,14 +241,13 @@ def rollout_backward(inst, traj, sT_bar=None, traj_bar=None, kappa=None):
     n, T = inst.n, inst.T
     el = model.elements(inst)
     lay = Layout(inst)
-    sb = np.zeros(6 * n) if sT_bar is None else np.array(sT_bar, dtype=np.float64)
+    sb = np.zeros(inst.n_s) if sT_bar is None else np.array(sT_bar, dtype=np.float64)
     if traj_bar is not None:
         sb = sb + traj_bar[T]
     ubar = np.zeros((T, 3 * len(inst.grip_nodes)))
     for t in range(T - 1, -1, -1):
         d = StepDerivative(inst, traj[t], inst.u[t], kappa, el, lay)
-        xb, vb, ub = d.vjp(sb[:3 * n], sb[3 * n:])
-        sb = np.concatenate([xb, vb])
+        sb, ub = d.vjp_s(sb)
         if traj_bar is not None:
             sb = sb + traj_bar[t]
         ubar[t] = ub
@@ -220,8 +269,7 @@ def rollout_jvp(inst, traj, ds0, du, kappa=None):
     out[0] = ds0
     for t in range(T):
         d = StepDerivative(inst, traj[t], inst.u[t], kappa, el, lay)
-        dxn, dvn = d.jvp(out[t][:3 * n], out[t][3 * n:], du[t])
-        out[t + 1] = np.vstack([dxn, dvn])
+        out[t + 1] = d.jvp_s(out[t], du[t])
     return out
 
 

@@ -3,9 +3,15 @@
 The step follows the paper's two-stage solver (paragraph "Simulation
 Solver"), with the readings stated below where the paper is silent.
 
-1. Grippers (eq. holonomic-constraint, grasp taken in its D -> infinity
-   limit): gripper k holds node j; x+_j = x_j + dt u_k, v+_j = u_k, and node j
-   is removed from the unknowns.
+1. Grippers (eq. holonomic-constraint).  Dirichlet mode (the grasp in its
+   D -> infinity limit): gripper k holds node j; x+_j = x_j + dt u_k,
+   v+_j = u_k, and node j is removed from the unknowns.  Penalty mode
+   (eq. dynamics-first-stage with the holonomic penalty and the smoothed
+   activation of the Contact Smoothing paragraph): the gripper position g_k
+   is part of the state, g+_k = g_k + dt u_k, node j stays free, and
+   F gains D_k (y_j - g+_k) with D_k = D_max exp(-|c_k| / kappa_h),
+   c_k = x_j - g_k (the constraint evaluated at the current state; for
+   kappa_h = 0 the indicator D_max [|c_k| <= r_g]).  D_k I enters P too.
 2. Predictor: x_hat = x + dt (1 - gamma) v.  gamma = 1 is exactly the paper's
    quasi-static eq. (dynamics) with M (q+ - q)/dt^2; gamma < 1 keeps a
    fraction of the velocity (damped implicit Euler).
@@ -59,6 +65,37 @@ class StepResult:
     newton_iters: int = 0
     ipm_iters: int = 0
     extra: dict = field(default_factory=dict)
+    g: np.ndarray = None   # (n_g, 3) next gripper positions (penalty mode)
+    pen: object = None     # Penalty data of the step (penalty mode)
+
+
+@dataclass
+class Penalty:
+    """Penalty grasp of one step: gripper k pulls node nodes[k] towards
+    gplus[k] with stiffness D[k]; dD[k] = dD_k / dc_k, c_k = x_j - g_k."""
+    nodes: np.ndarray
+    D: np.ndarray
+    dD: np.ndarray
+    gplus: np.ndarray
+
+
+def grasp_activation(inst, x, g):
+    """D_k and dD_k/dc_k for every gripper (c_k = x_j - g_k).  The
+    derivative of |c| at c = 0 is taken as 0; the hard indicator has zero
+    derivative."""
+    ng = len(inst.grip_nodes)
+    D = np.zeros(ng)
+    dD = np.zeros((ng, 3))
+    for k, j in enumerate(inst.grip_nodes):
+        c = x[j] - g[k]
+        r = float(np.sqrt(c @ c))
+        if inst.kappa_h > 0.0:
+            D[k] = inst.D_max * np.exp(-r / inst.kappa_h)
+            if r > 0.0:
+                dD[k] = -D[k] / inst.kappa_h * c / r
+        else:
+            D[k] = inst.D_max if r <= inst.r_g else 0.0
+    return D, dD
 
 
 class Layout:
@@ -67,9 +104,11 @@ class Layout:
     def __init__(self, inst):
         n = inst.n
         self.n = n
+        self.penalty = getattr(inst, "grip_mode", "dirichlet") == "penalty"
         self.grip_of = -np.ones(n, dtype=np.int64)
-        for k, j in enumerate(inst.grip_nodes):
-            self.grip_of[j] = k
+        if not self.penalty:
+            for k, j in enumerate(inst.grip_nodes):
+                self.grip_of[j] = k
         self.free = self.grip_of < 0
         self.free_nodes = np.nonzero(self.free)[0]
         self.grip_nodes = np.array(inst.grip_nodes, dtype=np.int64)
@@ -94,44 +133,55 @@ def gripper_targets(inst, lay: Layout, x, u_t):
     return b
 
 
-def psi_gradient(inst, el, lay, y, xhat):
+def psi_gradient(inst, el, lay, y, xhat, pen=None):
     """F(y) of eq. (dynamics-first-stage) on the free nodes, zero elsewhere."""
     F = model.gradient(el, y)
     F = F + inst.mass / inst.dt ** 2 * (y - xhat) - inst.mass * inst.gravity[None, :]
+    if pen is not None:
+        for k, j in enumerate(pen.nodes):
+            F[j] += pen.D[k] * (y[j] - pen.gplus[k])
     F[~lay.free] = 0.0
     return F
 
 
-def psi_difference(inst, el, lay, y0, y1, xhat):
+def psi_difference(inst, el, lay, y0, y1, xhat, pen=None):
     """Psi(y1) - Psi(y0) in cancellation-free form."""
     dE = model.energy_difference(el, y0, y1)
     f = lay.free
     dy = (y1 - y0)[f]
     dM = inst.mass / (2.0 * inst.dt ** 2) * np.sum(dy * (y1[f] + y0[f] - 2.0 * xhat[f]))
     dG = -inst.mass * np.sum(dy @ inst.gravity)
-    return dE + dM + dG
+    dP = 0.0
+    if pen is not None:
+        for k, j in enumerate(pen.nodes):
+            dP += 0.5 * pen.D[k] * float((y1[j] - y0[j]) @ (y1[j] + y0[j] - 2.0 * pen.gplus[k]))
+    return dE + dM + dG + dP
 
 
-def psi_hessian_ff(inst, el, lay, y, project):
+def psi_hessian_ff(inst, el, lay, y, project, pen=None):
     """d^2 Psi / dy^2 restricted to the free DoFs (sparse)."""
     H = model.hessian(el, y, project=project)
-    Hff = H[lay.fidx][:, lay.fidx] + sp.diags(mass_diag(inst, lay))
+    d = mass_diag(inst, lay).copy()
+    if pen is not None:
+        for k, j in enumerate(pen.nodes):
+            d[3 * lay.fpos[j]:3 * lay.fpos[j] + 3] += pen.D[k]
+    Hff = H[lay.fidx][:, lay.fidx] + sp.diags(d)
     return Hff.tocsc()
 
 
-def stage1(inst, el, lay, y0, xhat, max_iter=100):
+def stage1(inst, el, lay, y0, xhat, max_iter=100, pen=None):
     """Newton's method on F(y) = 0 (minimising Psi) from y0."""
     y = y0.copy()
     scale = 1.0 + inst.mass * float(np.max(np.abs(inst.gravity)))
     tol = 1e-10 * scale
     it = 0
     for it in range(max_iter):
-        F = psi_gradient(inst, el, lay, y, xhat)
+        F = psi_gradient(inst, el, lay, y, xhat, pen)
         if not np.all(np.isfinite(F)):
             return y, STATUS_NONFINITE, it
         if np.max(np.abs(F), initial=0.0) <= tol:
             return y, STATUS_OK, it
-        Hp = psi_hessian_ff(inst, el, lay, y, project=True)
+        Hp = psi_hessian_ff(inst, el, lay, y, project=True, pen=pen)
         g = F.ravel()[lay.fidx]
         d = spla.spsolve(Hp, -g)
         D = np.zeros(3 * inst.n)
@@ -140,13 +190,13 @@ def stage1(inst, el, lay, y0, xhat, max_iter=100):
         gTd = float(g @ d)
         alpha = 1.0
         for _ in range(60):
-            if psi_difference(inst, el, lay, y, y + alpha * D, xhat) <= 1e-4 * alpha * gTd:
+            if psi_difference(inst, el, lay, y, y + alpha * D, xhat, pen) <= 1e-4 * alpha * gTd:
                 break
             alpha *= 0.5
         y = y + alpha * D
         if np.max(np.abs(alpha * D)) <= 1e-16 * (1.0 + np.max(np.abs(y))):
             break
-    F = psi_gradient(inst, el, lay, y, xhat)
+    F = psi_gradient(inst, el, lay, y, xhat, pen)
     ok = np.max(np.abs(F), initial=0.0) <= 1e3 * tol
     return y, (STATUS_OK if ok else STATUS_NEWTON_NOCONV), it + 1
 
@@ -247,14 +297,20 @@ def hard_crossover(P, N, phi, D, lam, gap, fscale, xscale):
     return D2, lam2, gap2, act, ok
 
 
-def step(inst, x, v, u_t, kappa, el=None, lay=None) -> StepResult:
-    """q+ = f(q, u) with contact relaxation kappa (kappa = 0: hard contact)."""
+def step(inst, x, v, u_t, kappa, el=None, lay=None, g=None) -> StepResult:
+    """q+ = f(q, u) with contact relaxation kappa (kappa = 0: hard contact).
+    Penalty mode needs the gripper positions g (n_g, 3)."""
     el = model.elements(inst) if el is None else el
     lay = Layout(inst) if lay is None else lay
     dt, gamma = inst.dt, inst.gamma
     x = np.asarray(x, dtype=np.float64).reshape(inst.n, 3)
     v = np.asarray(v, dtype=np.float64).reshape(inst.n, 3)
     u = np.asarray(u_t, dtype=np.float64).reshape(-1, 3)
+    pen = None
+    if lay.penalty:
+        g = np.asarray(g, dtype=np.float64).reshape(-1, 3)
+        D, dD = grasp_activation(inst, x, g)
+        pen = Penalty(np.array(inst.grip_nodes, dtype=np.int64), D, dD, g + dt * u)
     b = gripper_targets(inst, lay, x, u)
     xhat = x + dt * (1.0 - gamma) * v
     y0 = xhat.copy()
@@ -266,11 +322,11 @@ def step(inst, x, v, u_t, kappa, el=None, lay=None) -> StepResult:
         return StepResult(nan, nan, nan, nan, xhat, e.astype(int), e.astype(int), e,
                           np.zeros((0, 3)), np.zeros((0, 3, 3)), e, e, e.astype(bool),
                           kappa, STATUS_NONFINITE)
-    y, st1, it1 = stage1(inst, el, lay, y0, xhat)
+    y, st1, it1 = stage1(inst, el, lay, y0, xhat, pen=pen)
     status = max(status, st1)
 
     pn, po, phi, nrm, curv = contact_pairs(inst, lay, y)
-    P = psi_hessian_ff(inst, el, lay, y, project=False)
+    P = psi_hessian_ff(inst, el, lay, y, project=False, pen=pen)
     fscale = inst.mass / dt ** 2 * inst.h + inst.mass * float(np.max(np.abs(inst.gravity)))
     xscale = inst.h
     delta = np.zeros((inst.n, 3))
@@ -297,30 +353,40 @@ def step(inst, x, v, u_t, kappa, el=None, lay=None) -> StepResult:
     xn = y + delta
     xn[~lay.free] = b[~lay.free]
     vn = (xn - x) / dt
-    for k, j in enumerate(inst.grip_nodes):
-        vn[j] = u[k]
+    if not lay.penalty:
+        for k, j in enumerate(inst.grip_nodes):
+            vn[j] = u[k]
     if not (np.all(np.isfinite(xn)) and np.all(np.isfinite(vn))):
         status = STATUS_NONFINITE
     return StepResult(xn, vn, y, delta, xhat, pn, po, phi, nrm, curv, lam, gap, active,
-                      kappa, status, it1, it2)
+                      kappa, status, it1, it2, g=None if pen is None else pen.gplus, pen=pen)
+
+
+def split_state(inst, s):
+    """s = [x | v] (+ [g] in penalty mode) -> x (n, 3), v (n, 3), g (n_g, 3) or None."""
+    n = inst.n
+    s = np.asarray(s, dtype=np.float64)
+    g = s[6 * n:].reshape(-1, 3) if getattr(inst, "grip_mode", "dirichlet") == "penalty" else None
+    return s[:3 * n].reshape(n, 3), s[3 * n:6 * n].reshape(n, 3), g
 
 
 def rollout(inst, kappa=None, s0=None, u=None):
-    """Roll out inst.T steps.  Returns (traj (T+1, 6n), status per step)."""
+    """Roll out inst.T steps.  Returns (traj (T+1, n_s), status per step)."""
     kappa = inst.kappa_fwd if kappa is None else kappa
     s0 = inst.s0 if s0 is None else s0
     u = inst.u if u is None else u
     el = model.elements(inst)
     lay = Layout(inst)
     n = inst.n
-    traj = np.zeros((inst.T + 1, 6 * n))
+    traj = np.zeros((inst.T + 1, inst.n_s))
     traj[0] = s0
     stat = np.zeros(inst.T, dtype=np.int64)
     for t in range(inst.T):
-        x = traj[t, :3 * n].reshape(n, 3)
-        v = traj[t, 3 * n:].reshape(n, 3)
-        r = step(inst, x, v, u[t], kappa, el, lay)
+        x, v, g = split_state(inst, traj[t])
+        r = step(inst, x, v, u[t], kappa, el, lay, g=g)
         traj[t + 1, :3 * n] = r.x.ravel()
-        traj[t + 1, 3 * n:] = r.v.ravel()
+        traj[t + 1, 3 * n:6 * n] = r.v.ravel()
+        if r.g is not None:
+            traj[t + 1, 6 * n:] = r.g.ravel()
         stat[t] = r.status
     return traj, stat

@@ -18,4 +18,5 @@ from .gen import (  # noqa: F401
     small_cloth_batch,
     random_cotangent,
     serve_trace,
+    penalty_grasp,
 )

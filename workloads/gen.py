@@ -40,7 +40,7 @@ class Instance:
     k_struct: float           # stretch / structural spring stiffness [N/m]
     k_shear: float            # cloth shear spring stiffness [N/m] (rope: unused)
     k_bend: float             # rope: discrete-curvature stiffness; cloth: bend spring [N/m]
-    grip_nodes: tuple         # node held by gripper k (Dirichlet grasp)
+    grip_nodes: tuple         # node held by gripper k
     ground: bool              # plane z = 0
     spheres: np.ndarray       # (ns, 4): cx, cy, cz, r
     boxes: np.ndarray         # (nb, 7): cx, cy, cz, hx, hy, hz, rounding
@@ -50,16 +50,28 @@ class Instance:
     kappa_fwd: float          # contact relaxation used by forward rollouts [J]
     kappa_bwd: float          # contact relaxation used for derivatives [J]
     T: int                    # horizon
-    s0: np.ndarray            # (6n,) initial state
+    s0: np.ndarray            # (n_s,) initial state [x | v] (+ [g] in penalty mode)
     u: np.ndarray             # (T, 3 * n_grip) controls
+    # grasp: "dirichlet" (node held exactly) or "penalty" (gripper position
+    # g_k is part of the state and pulls its node with stiffness
+    # D_k = D_max * activation; smooth activation exp(-|x_j - g_k| / kappa_h)
+    # if kappa_h > 0, else the indicator of |x_j - g_k| <= r_g)
+    grip_mode: str = "dirichlet"
+    D_max: float = 0.0        # [N/m]
+    kappa_h: float = 0.0      # [m]
+    r_g: float = 0.0          # [m]
 
     @property
     def n(self) -> int:
         return self.nx * self.ny
 
     @property
+    def penalty(self) -> bool:
+        return self.grip_mode == "penalty"
+
+    @property
     def n_s(self) -> int:
-        return 6 * self.n
+        return 6 * self.n + (3 * len(self.grip_nodes) if self.penalty else 0)
 
     @property
     def n_u(self) -> int:
@@ -197,6 +209,22 @@ def config_c1(seed: int = 1001) -> Instance:
     u = rng.normal(0.0, 0.05, size=(T, 3))
     return rope(20, k=500.0, k_bend=5.0, mass=0.01, dt=0.005, gamma=0.02, T=T,
                 spheres=[[0.4, 0.0, 0.05, 0.05]], u=u)
+
+
+def penalty_grasp(inst: Instance, *, offset_scale: float = 0.003, kappa_h: float = 0.01,
+                  r_g: float = 0.005, D_max: float = None, seed: int = 0) -> Instance:
+    """The same instance with penalty grasps: gripper k starts near its node
+    (seeded offset ~ N(0, offset_scale^2) per axis) and joins the state;
+    D_max defaults to 100 m / dt^2.  kappa_h = 0 selects the hard activation
+    radius r_g."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = inst.n
+    x0 = np.asarray(inst.s0[:3 * n]).reshape(n, 3)
+    g0 = np.array([x0[j] for j in inst.grip_nodes]) + rng.normal(0.0, offset_scale,
+                                                                 size=(len(inst.grip_nodes), 3))
+    D = 100.0 * inst.mass / inst.dt ** 2 if D_max is None else D_max
+    s0 = np.concatenate([np.asarray(inst.s0[:6 * n]), g0.ravel()])
+    return inst.replace(grip_mode="penalty", D_max=float(D), kappa_h=float(kappa_h), r_g=float(r_g), s0=s0)
 
 
 def _c2_instance(rng, n=64, T=100) -> Instance:
