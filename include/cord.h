@@ -36,9 +36,20 @@
  * State layout of one instance with n nodes and n_grip grippers
  *   s = [x_0 .. x_{n-1} | v_0 .. v_{n-1}]   (xyz interleaved), n_s = 6 n
  *   u = [u_0 | .. | u_{n_grip-1}]           (gripper velocities), n_u = 3 n_grip
- * Grippers hold their node rigidly (the D -> infinity limit of the
- * holonomic penalty of eq. (dynamics-first-stage)): x+_j = x_j + dt u_k,
- * v+_j = u_k.
+ * Grasp modes (cord_instance_desc.grip_mode):
+ *   CORD_GRIP_DIRICHLET  grippers hold their node rigidly (the D -> infinity
+ *                        limit of the holonomic penalty of eq.
+ *                        (dynamics-first-stage)): x+_j = x_j + dt u_k,
+ *                        v+_j = u_k.
+ *   CORD_GRIP_PENALTY    the penalty of eq. (dynamics-first-stage) with the
+ *                        smoothed activation of Sec. 4.1 "Contact Smoothing":
+ *                        gripper positions join the state,
+ *                        s = [x | v | g_0 .. g_{n_grip-1}], n_s = 6 n + 3 n_grip,
+ *                        g+_k = g_k + dt u_k; node j of gripper k stays free
+ *                        and is pulled towards g+_k with stiffness
+ *                        D_k = D_max exp(-|x_j - g_k| / kappa_h)
+ *                        (kappa_h = 0: D_max if |x_j - g_k| <= r_g, else 0),
+ *                        which also enters P of eq. (dynamics-second-stage).
  *
  * Batches may be ragged (different n, T per instance).  Every I/O buffer is
  * the concatenation of per-instance blocks in instance order; the block
@@ -80,6 +91,9 @@ extern "C" {
 #define CORD_ROPE   0
 #define CORD_CLOTH  1
 
+#define CORD_GRIP_DIRICHLET 0
+#define CORD_GRIP_PENALTY   1
+
 /*
  * Physical parameters of one instance.
  *   dt        time step [s], > 0
@@ -119,6 +133,10 @@ typedef struct {
  *   sphere    (cx, cy, cz, r) with r > 0
  *   box       (cx, cy, cz, hx, hy, hz, rho): axis-aligned box of half
  *             extents h with edges rounded by rho, 0 <= rho < min(h)
+ *   grip_mode CORD_GRIP_DIRICHLET or CORD_GRIP_PENALTY (see the state layout)
+ *   D_max     penalty mode: grasp stiffness at full activation [N/m], > 0
+ *   kappa_h   penalty mode: activation length [m], >= 0 (0: hard activation)
+ *   r_g       penalty mode: hard activation radius [m], > 0 when kappa_h = 0
  */
 typedef struct {
     int32_t kind;
@@ -135,6 +153,10 @@ typedef struct {
     int32_t n_box;
     float box[CORD_MAX_BOX][7];
     cord_params params;
+    int32_t grip_mode;
+    float D_max;
+    float kappa_h;
+    float r_g;
 } cord_instance_desc;
 
 typedef struct cord_sim cord_sim;

@@ -26,6 +26,7 @@ ST_OK, ST_NEWTON_NOCONV, ST_NOT_PD, ST_QP_NOCONV, ST_NONFINITE = range(5)
 MAX_GRIP, MAX_SPHERE, MAX_BOX, MAX_OBST = 4, 4, 2, 4
 ROPE, CLOTH = 0, 1
 STORE_FULL, STORE_CKPT, STORE_FINAL = 0, 1, 2
+GRIP_DIRICHLET, GRIP_PENALTY = 0, 1
 LAUNCH_GROUPED, LAUNCH_PER_INSTANCE, LAUNCH_PERSISTENT, LAUNCH_GRAPH = 0, 1, 2, 3
 
 
@@ -39,7 +40,8 @@ class InstanceDesc(ctypes.Structure):
                 ("h", c_float), ("mass", c_float), ("k_struct", c_float), ("k_shear", c_float),
                 ("k_bend", c_float), ("n_grip", c_int32), ("grip_node", c_int32 * MAX_GRIP),
                 ("ground", c_int32), ("n_sphere", c_int32), ("sphere", (c_float * 4) * MAX_SPHERE),
-                ("n_box", c_int32), ("box", (c_float * 7) * MAX_BOX), ("params", Params)]
+                ("n_box", c_int32), ("box", (c_float * 7) * MAX_BOX), ("params", Params),
+                ("grip_mode", c_int32), ("D_max", c_float), ("kappa_h", c_float), ("r_g", c_float)]
 
 
 class SimInfo(ctypes.Structure):

@@ -26,7 +26,8 @@ def _stream():
 def make_desc(inst) -> L.InstanceDesc:
     """Fill a cord_instance_desc from an object with the attributes of
     workloads.Instance (kind, nx, ny, h, mass, k_*, grip_nodes, ground,
-    spheres, boxes, dt, gamma, gravity, kappa_fwd, kappa_bwd, T)."""
+    spheres, boxes, dt, gamma, gravity, kappa_fwd, kappa_bwd, T, and
+    grip_mode, D_max, kappa_h, r_g for the penalty grasp)."""
     d = L.InstanceDesc()
     d.kind = L.ROPE if inst.kind == "rope" else L.CLOTH
     d.nx, d.ny, d.T = int(inst.nx), int(inst.ny), int(inst.T)
@@ -55,6 +56,9 @@ def make_desc(inst) -> L.InstanceDesc:
     for c in range(3):
         p.gravity[c] = float(inst.gravity[c])
     p.kappa_fwd, p.kappa_bwd, p.mu = float(inst.kappa_fwd), float(inst.kappa_bwd), 0.0
+    if getattr(inst, "grip_mode", "dirichlet") == "penalty":
+        d.grip_mode = L.GRIP_PENALTY
+        d.D_max, d.kappa_h, d.r_g = float(inst.D_max), float(inst.kappa_h), float(inst.r_g)
     return d
 
 
@@ -76,7 +80,7 @@ class Sim:
         self.B = B
         self.n = [i.n for i in self.instances]
         self.T = [i.T for i in self.instances]
-        self.n_s = [6 * i.n for i in self.instances]
+        self.n_s = [int(i.n_s) for i in self.instances]
         self.n_u = [3 * len(i.grip_nodes) for i in self.instances]
         self._off_cache = {}
 

@@ -53,17 +53,19 @@ const int kRopeBuckets[] = {32, 64, 128, 256};
 const int kClothBuckets[] = {64, 128, 256, 512, 1024};
 
 // Dense A_t/B_t of rope classes go to the banded direct kernel; JVPs, cloth,
-// B_t alone and classes it does not cover use the class's iterative kernel.
+// B_t alone, penalty grasps and classes it does not cover use the class's
+// iterative kernel.
 // Setting CORD_LINEARIZE_ITERATIVE=1 in the environment forces the iterative
 // kernel everywhere (for comparisons).
-hipError_t launch_linearize(int cfg_index, int topo, int nmax, const KArgs& a, int nblk, int tmax, hipStream_t st) {
+hipError_t launch_linearize(int cfg_index, int topo, int nmax, bool penalty, const KArgs& a, int nblk, int tmax,
+                            hipStream_t st) {
     static const bool iterative = [] {
         const char* e = std::getenv("CORD_LINEARIZE_ITERATIVE");
         return e && e[0] == '1';
     }();
     int count = 0;
     const KernelCfg* cfg = kernel_configs(&count);
-    if (a.A && topo == kRope && !iterative) {
+    if (a.A && topo == kRope && !penalty && !iterative) {
         KArgs ad = a;
         ad.jvp_k = 0; ad.jvp_ds = nullptr; ad.jvp_du = nullptr; ad.jvp_out = nullptr;
         bool handled = false;
@@ -98,6 +100,7 @@ struct Group {
     int32_t* d_ids = nullptr;
     int tmax = 0;
     int cap[2] = {1, 1};       // persistent grid: resident workgroups (rollout, backward)
+    bool penalty = false;      // some instance uses the penalty grasp
 };
 
 enum Op { kOpRollout = 0, kOpBackward = 1 };
@@ -164,6 +167,13 @@ int validate(const cord_instance_desc& d, int i) {
     }
     const int nobs = (d.ground ? 1 : 0) + d.n_sphere + d.n_box;
     if (nobs > CORD_MAX_OBST) return fail(CORD_EUNSUPPORTED, "instance %d: %d obstacles > %d", i, nobs, CORD_MAX_OBST);
+    if (d.grip_mode != CORD_GRIP_DIRICHLET && d.grip_mode != CORD_GRIP_PENALTY)
+        return fail(CORD_EINVAL, "instance %d: unknown grip_mode %d", i, d.grip_mode);
+    if (d.grip_mode == CORD_GRIP_PENALTY) {
+        if (!(d.D_max > 0.f) || !std::isfinite(d.D_max)) return fail(CORD_EINVAL, "instance %d: penalty grasp needs D_max > 0", i);
+        if (!(d.kappa_h >= 0.f) || !std::isfinite(d.kappa_h)) return fail(CORD_EINVAL, "instance %d: kappa_h must be >= 0", i);
+        if (d.kappa_h == 0.f && !(d.r_g > 0.f)) return fail(CORD_EINVAL, "instance %d: hard activation needs r_g > 0", i);
+    }
     if (bucket_of(d.kind == CORD_ROPE ? kRope : kCloth, n) < 0)
         return fail(CORD_EUNSUPPORTED, "instance %d: %d nodes exceed every kernel configuration", i, n);
     return CORD_OK;
@@ -175,7 +185,9 @@ void fill_instdev(const cord_instance_desc& d, InstDev& I) {
     I.kind = d.kind == CORD_ROPE ? kRope : kCloth;
     I.nx = d.nx; I.ny = d.ny; I.n = d.nx * d.ny;
     I.T = d.T; I.n_grip = d.n_grip;
-    I.n_s = 6 * I.n; I.n_u = 3 * d.n_grip;
+    I.grip_mode = d.grip_mode == CORD_GRIP_PENALTY ? 1 : 0;
+    I.n_s = 6 * I.n + (I.grip_mode ? 3 * d.n_grip : 0); I.n_u = 3 * d.n_grip;
+    I.D_max = d.D_max; I.kappa_h = d.kappa_h; I.r_g = d.r_g;
     for (int g = 0; g < d.n_grip; ++g) I.grip_node[g] = d.grip_node[g];
     int o = 0;
     if (d.ground) { I.obs_type[o] = kObsGround; ++o; }
@@ -481,6 +493,7 @@ int cord_sim_create(const cord_instance_desc* inst, int32_t n_inst, cord_sim** o
         }
         const int gi = class_group[key];
         s->groups[gi].ids.push_back(i);
+        if (I.grip_mode) s->groups[gi].penalty = true;
         s->groups[gi].tmax = std::max(s->groups[gi].tmax, I.T);
         s->group_of[i] = gi;
     }
@@ -651,7 +664,7 @@ int cord_linearize(cord_sim* s, const float* traj, const float* u, float* A, flo
     for (const Group& g : s->groups) {
         a.ids = g.d_ids;
         a.n_ids = (int)g.ids.size();
-        CORD_HIP(launch_linearize(g.cfg, g.topo, g.nmax, a, a.n_ids, g.tmax, st));
+        CORD_HIP(launch_linearize(g.cfg, g.topo, g.nmax, g.penalty, a, a.n_ids, g.tmax, st));
     }
     return CORD_OK;
 }

@@ -11,5 +11,6 @@ int default_config(int topo, int nmax);
 int set_error(int code, const char* msg);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 struct KArgs;
-hipError_t launch_linearize(int cfg_index, int topo, int nmax, const KArgs& a, int nblk, int tmax, hipStream_t st);
+hipError_t launch_linearize(int cfg_index, int topo, int nmax, bool penalty, const KArgs& a, int nblk, int tmax,
+                            hipStream_t st);
 }  // namespace cord

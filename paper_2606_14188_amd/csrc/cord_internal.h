@@ -19,13 +19,14 @@ constexpr int kMaxGrip = 4;
 struct alignas(16) InstDev {
     int32_t kind, nx, ny, n;
     int32_t T, n_grip, n_obs, n_s;
-    int32_t n_u, pad0, pad1, pad2;
+    int32_t n_u, grip_mode, pad1, pad2;
     int32_t grip_node[kMaxGrip];
     int32_t obs_type[kMaxObs];
     float obs[kMaxObs][8];          // sphere: cx cy cz r; box: cx cy cz hx hy hz rho
     float h, mass, k_struct, k_shear;
     float k_bend, dt, gamma, kappa_fwd;
     float kappa_bwd, g0, g1, g2;
+    float D_max, kappa_h, r_g, pad3;
     int64_t s_off;      // sum n_s
     int64_t u_off;      // sum T n_u
     int64_t traj_off;   // sum (T+1) n_s

@@ -79,11 +79,14 @@ __device__ __forceinline__ void adjoint_step(Solver<TOPO, NT, PPT, NOBS>& S, con
     S.adjoint(xb, vb, ub, I.kappa_bwd, dxb);
 #pragma unroll
     for (int k = 0; k < PPT; ++k)
-        if (S.active(k) && !S.isfree(k)) {
+        if (S.has_grip(k)) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) a.u_bar[I.u_off + (int64_t)t * nu + 3 * S.grip[k] + c] = ub[k][c];
+            for (int c = 0; c < 3; ++c) a.u_bar[I.u_off + (int64_t)t * nu + 3 * S.grip_index(k) + c] = ub[k][c];
         }
-    if (a.traj_bar) add_cot<PPT>(xb, vb, a.traj_bar + I.traj_off + (int64_t)t * I.n_s, I.n, NT);
+    if (a.traj_bar) {
+        add_cot<PPT>(xb, vb, a.traj_bar + I.traj_off + (int64_t)t * I.n_s, I.n, NT);
+        S.set_gcot(a.traj_bar + I.traj_off + (int64_t)t * I.n_s, true);
+    }
 }
 
 template <int TOPO, int NT, int PPT, int NOBS>
@@ -104,6 +107,8 @@ __global__ __launch_bounds__(NT) void backward_kernel(KArgs a) {
             for (int c = 0; c < 3; ++c) { xb[k][c] = 0.f; vb[k][c] = 0.f; }
         if (a.traj_bar) add_cot<PPT>(xb, vb, a.traj_bar + I.traj_off + (int64_t)T * ns, n, NT);
         else if (a.sT_bar) add_cot<PPT>(xb, vb, a.sT_bar + I.s_off, n, NT);
+        S.set_gcot(a.traj_bar ? a.traj_bar + I.traj_off + (int64_t)T * ns : (a.sT_bar ? a.sT_bar + I.s_off : nullptr),
+                   false);
 
         if (a.store == CORD_STORE_FULL) {
             for (int t = T - 1; t >= 0; --t) {
@@ -141,6 +146,7 @@ __global__ __launch_bounds__(NT) void backward_kernel(KArgs a) {
                 }
             }
         }
+        S.get_gcot(a.s0_bar + I.s_off);
         if (threadIdx.x == 0) {
             if (a.status) a.status[id] = S.status;
             if (a.counters)
@@ -175,7 +181,7 @@ __global__ __launch_bounds__(NT) void linearize_kernel(KArgs a) {
             const int pr = r / 3, cr = r - 3 * pr;
             int gr = -1;
             for (int j = 0; j < I.n_grip; ++j)
-                if (I.grip_node[j] == pr) gr = j;
+                if (I.grip_node[j] == pr && !I.grip_mode) gr = j;
             float* Ax = A ? A + (int64_t)r * ns : nullptr;
             float* Av = A ? A + (int64_t)(3 * n + r) * ns : nullptr;
             if (gr >= 0) {
@@ -206,6 +212,7 @@ __global__ __launch_bounds__(NT) void linearize_kernel(KArgs a) {
                 for (int c = 0; c < 3; ++c) { xb[k][c] = (p == pr && c == cr) ? 1.f : 0.f; vb[k][c] = 0.f; }
             }
             float dxb[PPT][3];
+            S.set_gcot(nullptr, false);
             S.adjoint(xb, vb, ub, kb, dxb);
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
@@ -221,13 +228,31 @@ __global__ __launch_bounds__(NT) void linearize_kernel(KArgs a) {
                         Av[3 * n + 3 * p + c] = vb[k][c] * idt;
                     }
                 }
-                if (Bm && S.active(k) && !S.isfree(k)) {
+                if (Bm && S.has_grip(k)) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        Bm[(int64_t)r * nu + 3 * S.grip[k] + c] = ub[k][c];
-                        Bm[(int64_t)(3 * n + r) * nu + 3 * S.grip[k] + c] = ub[k][c] * idt;
+                        Bm[(int64_t)r * nu + 3 * S.grip_index(k) + c] = ub[k][c];
+                        Bm[(int64_t)(3 * n + r) * nu + 3 * S.grip_index(k) + c] = ub[k][c] * idt;
                     }
                 }
+                // penalty grasp: columns of the gripper positions
+                if (A && S.pen[k] >= 0) {
+                    const float* G = S.pg(k);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        Ax[6 * n + 3 * S.pen[k] + c] = G[10 + c];
+                        Av[6 * n + 3 * S.pen[k] + c] = G[10 + c] * idt;
+                    }
+                }
+            }
+        }
+        if (I.grip_mode) {
+            // rows of g+ = g + dt u
+            for (int r = 6 * n; r < ns; ++r) {
+                if (A)
+                    for (int col = threadIdx.x; col < ns; col += NT) A[(int64_t)r * ns + col] = col == r ? 1.f : 0.f;
+                if (Bm)
+                    for (int col = threadIdx.x; col < nu; col += NT) Bm[(int64_t)r * nu + col] = col == r - 6 * n ? dt : 0.f;
             }
         }
     }
@@ -245,10 +270,16 @@ __global__ __launch_bounds__(NT) void linearize_kernel(KArgs a) {
                 for (int c = 0; c < 3; ++c) {
                     dx[k][c] = (a.jvp_ds && p < n) ? a.jvp_ds[sbase + 3 * p + c] : 0.f;
                     dv[k][c] = (a.jvp_ds && p < n) ? a.jvp_ds[sbase + 3 * n + 3 * p + c] : 0.f;
-                    du[k][c] = (a.jvp_du && S.active(k) && !S.isfree(k)) ? a.jvp_du[ubase + 3 * S.grip[k] + c] : 0.f;
+                    du[k][c] = (a.jvp_du && S.has_grip(k)) ? a.jvp_du[ubase + 3 * S.grip_index(k) + c] : 0.f;
                 }
+                if (S.pen[k] >= 0)
+                    for (int c = 0; c < 3; ++c) S.pg(k)[13 + c] = a.jvp_ds ? a.jvp_ds[sbase + 6 * n + 3 * S.pen[k] + c] : 0.f;
             }
             S.tangent(dx, dv, du, ox, ov, kb);
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+                if (S.pen[k] >= 0)
+                    for (int c = 0; c < 3; ++c) a.jvp_out[sbase + 6 * n + 3 * S.pen[k] + c] = S.pg(k)[13 + c];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const int p = (int)threadIdx.x + k * NT;

@@ -103,7 +103,7 @@ struct Req {
     cord_plan_request r{};
     std::vector<float> s0, u_warm, u_init;
     int state = kQueued;
-    int T = 0, ns = 0, nu = 0, C = 0, cfg = -1;
+    int T = 0, n = 0, ns = 0, nu = 0, C = 0, cfg = -1;
     size_t footprint = 0;
     std::vector<std::pair<size_t, size_t>> blocks;
     int slot = -1;
@@ -365,7 +365,8 @@ bool enqueue(cord_server* s, Req* q) {
         l.lin_zero_off = 1;
         l.status = nullptr;
         const int topo = q->r.inst.kind == CORD_ROPE ? kRope : kCloth;
-        SRV_HIP(launch_linearize(q->cfg, topo, bucket_of(topo, q->ns / 6), l, 1, T, st));
+        SRV_HIP(launch_linearize(q->cfg, topo, bucket_of(topo, q->n), q->r.inst.grip_mode == CORD_GRIP_PENALTY, l, 1,
+                                 T, st));
     }
     // result download into the slot's staging
     char* h = sg.down;
@@ -559,7 +560,8 @@ int cord_plan_submit(cord_server* s, const cord_plan_request* r, uint64_t* ticke
     if (!q) return set_error(CORD_ENOMEM, "host allocation");
     q->r = *r;
     q->T = d.T;
-    q->ns = 6 * n;
+    q->n = n;
+    q->ns = 6 * n + (d.grip_mode == CORD_GRIP_PENALTY ? 3 * d.n_grip : 0);
     q->nu = 3 * d.n_grip;
     q->C = r->n_cand;
     const int topo = d.kind == CORD_ROPE ? kRope : kCloth;

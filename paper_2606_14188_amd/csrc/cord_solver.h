@@ -212,7 +212,7 @@ template <> struct Topo<kCloth> {
 
 // LDS floats used by one workgroup.
 template <int NT, int PPT>
-constexpr int lds_floats() { return 12 * NT * PPT + 64; }
+constexpr int lds_floats() { return 12 * NT * PPT + 64 + 16 * kMaxGrip; }
 
 // ----------------------------------------------------------------- solver
 template <int TOPO, int NT, int PPT, int NOBS>
@@ -227,6 +227,8 @@ struct Solver {
     float* V;    // exchange vector (CG direction, adjoints, tangents)
     float* DL;   // stage-2 correction / line-search step
     float* rb;   // reduction scratch (2 x 16)
+    float* GR;   // penalty grasp, 16 floats per gripper (read and written only by
+                 // the thread owning its node): g, g+, D, dD/dc, cotangent of g, tangent of g
     int rslot;
 
     // instance constants
@@ -239,6 +241,9 @@ struct Solver {
 
     // particles
     int grip[PPT];          // -1 free, else gripper index; -2 inactive slot
+    int pen[PPT];           // penalty grasp: gripper pulling this (free) particle, or -1
+    int pmode;
+    float Dmax, khal, rgrip;
     int px[PPT], py[PPT];   // grid coordinates (cloth)
     float x[PPT][3], v[PPT][3], d[PPT][3], dl[PPT][3], ug[PPT][3];
     float se[PPT][NS][3], sa[PPT][NS], sb[PPT][NS];
@@ -251,9 +256,14 @@ struct Solver {
     __device__ __forceinline__ int pidx(int k) const { return (int)threadIdx.x + k * NT; }
     __device__ __forceinline__ bool active(int k) const { return grip[k] != -2; }
     __device__ __forceinline__ bool isfree(int k) const { return grip[k] == -1; }
+    // particle k is moved by a gripper (either grasp mode) / that gripper's index
+    __device__ __forceinline__ bool has_grip(int k) const { return grip[k] >= 0 || pen[k] >= 0; }
+    __device__ __forceinline__ int grip_index(int k) const { return grip[k] >= 0 ? grip[k] : pen[k]; }
+    __device__ __forceinline__ float* pg(int k) const { return GR + 16 * pen[k]; }
 
     __device__ __forceinline__ void init(const InstDev& I, float* lds) {
-        X = lds; D = X + 3 * NM; V = D + 3 * NM; DL = V + 3 * NM; rb = DL + 3 * NM; rslot = 0;
+        X = lds; D = X + 3 * NM; V = D + 3 * NM; DL = V + 3 * NM; rb = DL + 3 * NM; GR = rb + 64; rslot = 0;
+        pmode = I.grip_mode; Dmax = I.D_max; khal = I.kappa_h; rgrip = I.r_g;
         n = I.n; nx = I.nx; ny = I.ny; ngrip = I.n_grip; nobs = I.n_obs;
         h = I.h; mass = I.mass; dt = I.dt; gam = I.gamma; mdt2 = I.mass / (I.dt * I.dt);
         kb = (TOPO == kRope) ? I.k_bend : 0.f;
@@ -277,7 +287,11 @@ struct Solver {
             int gk = (p < n) ? -1 : -2;
             for (int j = 0; j < I.n_grip; ++j)
                 if (I.grip_node[j] == p) gk = j;
-            grip[k] = gk;
+            // penalty grasp: the node stays free and its gripper is tracked in GR
+            pen[k] = (pmode && gk >= 0) ? gk : -1;
+            grip[k] = (pmode && gk >= 0) ? -1 : gk;
+            if (pen[k] >= 0)
+                for (int f = 0; f < 16; ++f) pg(k)[f] = 0.f;
             px[k] = (TOPO == kCloth) ? p % nx : p;
             py[k] = (TOPO == kCloth) ? p / nx : 0;
 #pragma unroll
@@ -364,6 +378,8 @@ struct Solver {
             if (active(k)) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { x[k][c] = s[3 * p + c]; v[k][c] = s[3 * n + 3 * p + c]; }
+                if (pen[k] >= 0)
+                    for (int c = 0; c < 3; ++c) pg(k)[c] = s[6 * n + 3 * pen[k] + c];
             }
         }
     }
@@ -374,8 +390,24 @@ struct Solver {
             if (active(k)) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { s[3 * p + c] = x[k][c]; s[3 * n + 3 * p + c] = v[k][c]; }
+                if (pen[k] >= 0)
+                    for (int c = 0; c < 3; ++c) s[6 * n + 3 * pen[k] + c] = pg(k)[c];
             }
         }
+    }
+
+    // penalty grasp: cotangent of the gripper positions (GR[10..12])
+    __device__ __forceinline__ void set_gcot(const float* s, bool add) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+            if (pen[k] >= 0)
+                for (int c = 0; c < 3; ++c) pg(k)[10 + c] = (add ? pg(k)[10 + c] : 0.f) + (s ? s[6 * n + 3 * pen[k] + c] : 0.f);
+    }
+    __device__ __forceinline__ void get_gcot(float* s) const {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+            if (pen[k] >= 0)
+                for (int c = 0; c < 3; ++c) s[6 * n + 3 * pen[k] + c] = pg(k)[10 + c];
     }
 
     // -------------------------------------------------- stage-1 pieces
@@ -400,6 +432,11 @@ struct Solver {
                 const float cv = dt * (1.f - gam);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) F[k][c] = mdt2 * (d[k][c] - cv * v[k][c]) - mass * g[c];
+                if (pen[k] >= 0) {
+                    const float* G = pg(k);
+                    for (int c = 0; c < 3; ++c) F[k][c] += G[6] * ((x[k][c] - G[3 + c]) + d[k][c]);
+                    Bd[k][0] += G[6]; Bd[k][3] += G[6]; Bd[k][5] += G[6];
+                }
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
@@ -463,6 +500,11 @@ struct Solver {
             if (isfree(k) && with_mass) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) q[k][c] = mdt2 * wp[c];
+            }
+            if (pen[k] >= 0) {
+                const float Dv = pg(k)[6];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) q[k][c] += Dv * wp[c];
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
@@ -614,6 +656,11 @@ struct Solver {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     acc += 0.5f * mdt2 * sp[c] * (2.f * (d[k][c] - cv * v[k][c]) + sp[c]) - mass * g[c] * sp[c];
+                if (pen[k] >= 0) {
+                    const float* G = pg(k);
+                    for (int c = 0; c < 3; ++c)
+                        acc += 0.5f * G[6] * sp[c] * (2.f * ((x[k][c] - G[3 + c]) + d[k][c]) + sp[c]);
+                }
             }
         }
         return bsum(acc);
@@ -635,6 +682,26 @@ struct Solver {
                 const float cv = dt * (1.f - gam);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) d[k][c] = cv * v[k][c] + dt * dt * g[c];
+                if (pen[k] >= 0) {
+                    // g+ = g + dt u; activation from c = x_j - g (the state before the step)
+                    float* G = pg(k);
+                    float cc[3];
+                    for (int c = 0; c < 3; ++c) {
+                        G[3 + c] = G[c] + dt * ut[3 * pen[k] + c];
+                        cc[c] = x[k][c] - G[c];
+                    }
+                    const float r = sqrtf(dot3(cc, cc));
+                    float Dv, sd;
+                    if (khal > 0.f) {
+                        Dv = Dmax * expf(-r / khal);
+                        sd = r > 0.f ? -Dv / (khal * r) : 0.f;
+                    } else {
+                        Dv = r <= rgrip ? Dmax : 0.f;
+                        sd = 0.f;
+                    }
+                    G[6] = Dv;
+                    for (int c = 0; c < 3; ++c) G[7 + c] = sd * cc[c];
+                }
             }
             put(X, k, x[k]);
             put(D, k, d[k]);
@@ -881,6 +948,8 @@ struct Solver {
                     x[k][c] = x[k][c] + inc;
                     v[k][c] = inc * idt;
                 }
+                if (pen[k] >= 0)
+                    for (int c = 0; c < 3; ++c) pg(k)[c] = pg(k)[3 + c];
             } else {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { x[k][c] = x[k][c] + dt * ug[k][c]; v[k][c] = ug[k][c]; }
@@ -1014,6 +1083,25 @@ struct Solver {
                     xb[k][c] += del[k][c];
                     ubk[k][c] = 0.f;
                 }
+                if (pen[k] >= 0) {
+                    // penalty grasp: D enters F (D (y - g+)) and P (D I); its
+                    // activation depends on c = x_j - g.  With z = K^{-1} qb
+                    // and mu = H^{-1}(...): Dbar = -z.Delta_j - mu.(y_j - g+),
+                    // g+bar = D mu + gbar, xbar_j += Dbar dD/dc,
+                    // gbar = g+bar - Dbar dD/dc, ubar = dt g+bar.
+                    float* G = pg(k);
+                    float Dbar = -dot3(z[k], dl[k]);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) Dbar -= mu[k][c] * ((x[k][c] - G[3 + c]) + d[k][c]);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const float gpb = G[6] * mu[k][c] + G[10 + c];
+                        xb[k][c] += Dbar * G[7 + c];
+                        dxb[k][c] += Dbar * G[7 + c];
+                        G[10 + c] = gpb - Dbar * G[7 + c];
+                        ubk[k][c] = dt * gpb;
+                    }
+                }
             } else {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -1057,6 +1145,20 @@ struct Solver {
         for (int k = 0; k < PPT; ++k)
 #pragma unroll
             for (int c = 0; c < 3; ++c) r1[k][c] = isfree(k) ? -t1[k][c] : 0.f;
+        // penalty grasp (tangent of g in GR[13..15]): dF gains
+        // dD (y - g+) - D dg+ with dD = dD/dc . (dx - dg), dg+ = dg + dt du
+        float pdk[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            pdk[k] = 0.f;
+            if (pen[k] < 0) continue;
+            const float* G = pg(k);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pdk[k] += G[7 + c] * (dx[k][c] - G[13 + c]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                r1[k][c] -= pdk[k] * ((x[k][c] - G[3 + c]) + d[k][c]) - G[6] * (G[13 + c] + dt * du[k][c]);
+        }
         build_precond<false>();
         if (!pcg<false>(r1, eps, kPcgTolAdj)) status = max(status, kStNotPD);
 #pragma unroll
@@ -1088,6 +1190,12 @@ struct Solver {
                 for (int c = 0; c < 3; ++c) r2[k][c] += clam[k][o] * cy[c] - s2 * cn[k][o][c];
             }
         }
+        // penalty grasp: P gains D I, so the stage-2 right-hand side gains -dD Delta_j
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+            if (pen[k] >= 0)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) r2[k][c] -= pdk[k] * dl[k][c];
         float eta[PPT][3];
         build_precond<true>();
         if (!pcg<true>(r2, eta, kPcgTolAdj)) status = max(status, kStNotPD);
@@ -1101,6 +1209,12 @@ struct Solver {
                 } else if (active(k)) { ox[k][c] = db[k][c]; ov[k][c] = du[k][c]; }
                 else { ox[k][c] = 0.f; ov[k][c] = 0.f; }
             }
+        // tangent of g+ replaces that of g
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+            if (pen[k] >= 0)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) pg(k)[13 + c] += dt * du[k][c];
     }
 };
 

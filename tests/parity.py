@@ -15,9 +15,12 @@ JAC_TOL = 1e-3
 
 
 def state_errors(traj, ref, n):
+    """Position and velocity errors; gripper positions (penalty grasp, after
+    the velocity block) count with the positions."""
     traj = np.asarray(traj, dtype=np.float64).reshape(ref.shape)
-    x, xr = traj[..., :3 * n], ref[..., :3 * n]
-    v, vr = traj[..., 3 * n:], ref[..., 3 * n:]
+    x = np.concatenate([traj[..., :3 * n], traj[..., 6 * n:]], axis=-1)
+    xr = np.concatenate([ref[..., :3 * n], ref[..., 6 * n:]], axis=-1)
+    v, vr = traj[..., 3 * n:6 * n], ref[..., 3 * n:6 * n]
     ex = np.max(np.abs(x - xr)) / max(np.max(np.abs(xr)), 1e-3)
     ev = np.max(np.abs(v - vr)) / max(np.max(np.abs(vr)), 1e-3)
     return float(ex), float(ev)

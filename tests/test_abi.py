@@ -75,6 +75,18 @@ def test_validation_errors(field, value, code):
     assert msg
 
 
+@pytest.mark.parametrize("mode,D_max,kappa_h,r_g,code", [
+    (7, 1.0, 0.01, 0.0, 1), (1, 0.0, 0.01, 0.0, 1), (1, 1.0, -0.1, 0.0, 1), (1, 1.0, 0.0, 0.0, 1),
+])
+def test_penalty_grasp_validation(mode, D_max, kappa_h, r_g, code):
+    from paper_2606_14188_amd.api import make_desc
+    d = make_desc(W.config_c1())
+    d.grip_mode, d.D_max, d.kappa_h, d.r_g = mode, D_max, kappa_h, r_g
+    rc, msg = _create([d])
+    assert rc == code, msg
+    assert msg
+
+
 def test_too_many_obstacles_unsupported():
     from paper_2606_14188_amd.api import make_desc
     inst = W.config_c1()

@@ -1,0 +1,107 @@
+"""GPU parity of the penalty grasp (holonomic penalty with smoothed or hard
+activation, gripper positions in the state) against the FP64 oracle:
+forward states, rollout gradients, dense A_t/B_t and JVP tangents, alone and
+in a batch that also holds Dirichlet-grasp instances of the same size class."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.derivatives import StepDerivative, rollout_backward
+from oracle.step import rollout as orollout
+from tests.parity import GRAD_TOL, JAC_TOL, STATE_TOL, rel_l2, state_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch():
+    """A penalty rope with smoothed activation (C1 geometry), a penalty rope
+    with hard activation, a penalty cloth and a Dirichlet rope in the same
+    class as the first."""
+    c1 = W.config_c1().replace(T=20)
+    c1 = c1.replace(u=c1.u[:20])
+    r_soft = W.penalty_grasp(c1, offset_scale=0.002, seed=11)
+    r_hard = W.penalty_grasp(W.small_rope_batch(1, 40, 12, seed=601)[0], offset_scale=0.002, kappa_h=0.0,
+                             r_g=0.005, seed=12)
+    cl = W.penalty_grasp(W.small_cloth_batch(1, 6, 5, 8, seed=602)[0], offset_scale=0.001, seed=13)
+    dr = W.small_rope_batch(1, 24, 10, seed=603)[0]
+    return [r_soft, r_hard, cl, dr]
+
+
+def _run(insts):
+    import torch
+    from paper_2606_14188_amd import Sim
+    sim = Sim(insts)
+    s0 = sim.pack_states([i.s0 for i in insts])
+    u = sim.pack_controls([i.u for i in insts])
+    st = torch.full((len(insts),), -1, dtype=torch.int32, device=sim.device)
+    traj = sim.rollout(s0, u, status=st)
+    torch.cuda.synchronize()
+    return sim, s0, u, traj, st.cpu().numpy()
+
+
+def test_penalty_forward_states():
+    insts = _batch()
+    sim, s0, u, traj, st = _run(insts)
+    assert (st == 0).all(), st
+    parts = sim.split(traj, "traj")
+    for i, inst in enumerate(insts):
+        ref, rst = orollout(inst)
+        assert rst.max() == 0
+        ex, ev = state_errors(parts[i], ref, inst.n)
+        print(f"{inst.kind} n={inst.n} {inst.grip_mode}: state err x {ex:.2e} v {ev:.2e}", flush=True)
+        assert ex <= STATE_TOL and ev <= STATE_TOL
+
+
+def test_penalty_gradient():
+    import torch
+    insts = _batch()
+    sim, s0, u, traj, st = _run(insts)
+    rng = np.random.default_rng(21)
+    cot = [rng.normal(size=i.n_s) for i in insts]
+    sT = sim.pack_states(cot)
+    s0b, ub = sim.backward(u, traj, sT_bar=sT)
+    torch.cuda.synchronize()
+    sp, up = sim.split(s0b, "s"), sim.split(ub, "u")
+    tp = sim.split(traj, "traj")
+    for i, inst in enumerate(insts):
+        tr = tp[i].reshape(inst.T + 1, inst.n_s).astype(np.float64)
+        sb_ref, ub_ref = rollout_backward(inst, tr, sT_bar=cot[i])
+        es, eu = rel_l2(sp[i], sb_ref), rel_l2(up[i], ub_ref)
+        print(f"{inst.kind} n={inst.n} {inst.grip_mode}: s0_bar err {es:.2e} u_bar err {eu:.2e}", flush=True)
+        assert es <= GRAD_TOL and eu <= GRAD_TOL
+
+
+def test_penalty_linearize_and_jvp():
+    import torch
+    insts = _batch()
+    sim, s0, u, traj, st = _run(insts)
+    status = torch.zeros(len(insts), dtype=torch.int32, device=sim.device)
+    k = 2
+    rng = np.random.default_rng(31)
+    ds = [rng.normal(size=(i.T, k, i.n_s)) for i in insts]
+    du = [rng.normal(size=(i.T, k, i.n_u)) for i in insts]
+    dst = sim.pack_states([d.ravel() for d in ds])
+    dut = sim.pack_states([d.ravel() for d in du])
+    A, Bm, out = sim.linearize(traj, u, jvp_k=k, jvp_ds=dst, jvp_du=dut, status=status)
+    torch.cuda.synchronize()
+    assert (status.cpu().numpy() == 0).all()
+    Ap, Bp, tp = sim.split(A, "A"), sim.split(Bm, "B"), sim.split(traj, "traj")
+    h = out.cpu().numpy()
+    off = 0
+    for j, inst in enumerate(insts):
+        ns, nu = inst.n_s, inst.n_u
+        Aj = Ap[j].reshape(inst.T, ns, ns)
+        Bj = Bp[j].reshape(inst.T, ns, nu)
+        blk = h[off:off + inst.T * k * ns].reshape(inst.T, k, ns)
+        off += inst.T * k * ns
+        tr = tp[j].reshape(inst.T + 1, ns).astype(np.float64)
+        for t in sorted({0, inst.T // 2, inst.T - 1}):
+            d = StepDerivative(inst, tr[t], inst.u[t], inst.kappa_bwd)
+            Ar, Br = d.dense()
+            ea = np.linalg.norm(Aj[t] - Ar) / np.linalg.norm(Ar)
+            eb = np.linalg.norm(Bj[t] - Br) / np.linalg.norm(Br)
+            ref = d.jvp_s(ds[j][t].T, du[j][t].T).T
+            ej = np.linalg.norm(blk[t] - ref) / np.linalg.norm(ref)
+            print(f"{inst.kind} n={inst.n} {inst.grip_mode} t={t}: A err {ea:.2e} B err {eb:.2e} jvp err {ej:.2e}",
+                  flush=True)
+            assert ea <= JAC_TOL and eb <= JAC_TOL and ej <= JAC_TOL
