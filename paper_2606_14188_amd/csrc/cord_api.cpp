@@ -50,7 +50,7 @@ int fail(int code, const char* fmt, ...) {
 namespace cord {
 // size classes: upper node counts per topology
 const int kRopeBuckets[] = {32, 64, 128, 256};
-const int kClothBuckets[] = {64, 128, 256, 512, 1024};
+const int kClothBuckets[] = {64, 128, 256, 512, 1024, 2304};
 
 // Dense A_t/B_t of rope classes go to the banded direct kernel; JVPs, cloth,
 // B_t alone, penalty grasps and classes it does not cover use the class's
@@ -83,7 +83,7 @@ hipError_t launch_linearize(int cfg_index, int topo, int nmax, bool penalty, con
 
 int bucket_of(int topo, int n) {
     const int* b = topo == kRope ? kRopeBuckets : kClothBuckets;
-    const int nb = topo == kRope ? 4 : 5;
+    const int nb = topo == kRope ? 4 : 6;
     for (int i = 0; i < nb; ++i)
         if (n <= b[i]) return b[i];
     return -1;

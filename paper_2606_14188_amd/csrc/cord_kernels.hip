@@ -11,11 +11,12 @@ namespace cord {
 const KernelCfg* rope_configs(int* count);
 const KernelCfg* cloth_configs_a(int* count);
 const KernelCfg* cloth_configs_b(int* count);
+const KernelCfg* cloth_configs_c(int* count);
 
 const KernelCfg* kernel_configs(int* count) {
     static const std::vector<KernelCfg> all = [] {
         std::vector<KernelCfg> v;
-        for (auto f : {rope_configs, cloth_configs_a, cloth_configs_b}) {
+        for (auto f : {rope_configs, cloth_configs_a, cloth_configs_b, cloth_configs_c}) {
             int c = 0;
             const KernelCfg* t = f(&c);
             v.insert(v.end(), t, t + c);

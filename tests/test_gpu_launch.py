@@ -94,12 +94,12 @@ def test_autotune_and_cache(tmp_path):
 
 
 def test_c4_mixed_batch_graph():
-    """4096 uneven instances (ropes 16..256 nodes, cloths with side capped at
-    32, T 30..120) in one graph launch; sampled instances against the
-    oracle, and one instance alone vs inside the mix (bitwise)."""
+    """4096 uneven instances (ropes 16..256 nodes, cloths 8x8..48x48, T
+    30..120) in one graph launch; sampled instances against the oracle, and
+    one instance alone vs inside the mix (bitwise)."""
     import torch
     from paper_2606_14188_amd import _lib as L, Sim
-    insts = W.config_c4(max_cloth_side=32)
+    insts = W.config_c4()
     sim, s0, u, sT = _setup(insts)
     sim.set_launch(L.LAUNCH_GRAPH)
     st = torch.full((len(insts),), -1, dtype=torch.int32, device=sim.device)

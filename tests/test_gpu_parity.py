@@ -336,3 +336,22 @@ def test_c2_linearize_full_size_sampled():
         eb = np.linalg.norm(Bj - Br) / np.linalg.norm(Br)
         print(f"C2 inst {j} t={t}: A err {ea:.2e} B err {eb:.2e}", flush=True)
         assert ea <= JAC_TOL and eb <= JAC_TOL
+
+
+def test_cloth_48x48_forward_and_gradient():
+    """A 48 x 48 cloth (2304 nodes, the three-particles-per-thread
+    configuration) over 4 steps: states and gradient against the oracle."""
+    import torch
+    insts = W.small_cloth_batch(1, 48, 48, 4, seed=481)
+    sim, s0, u, traj, st = _run(insts)
+    assert (st == 0).all()
+    _check_states(sim, traj, insts)
+    inst = insts[0]
+    cot = W.random_cotangent(inst.n_s, 482)
+    s0b, ub = sim.backward(u, traj, sT_bar=sim.pack_states([cot]))
+    torch.cuda.synchronize()
+    tr = sim.split(traj, "traj")[0].reshape(inst.T + 1, inst.n_s).astype(np.float64)
+    sb_ref, ub_ref = rollout_backward(inst, tr, sT_bar=cot)
+    es, eu = rel_l2(s0b.cpu().numpy(), sb_ref), rel_l2(ub.cpu().numpy(), ub_ref)
+    print(f"cloth 48x48: s0_bar err {es:.2e} u_bar err {eu:.2e}", flush=True)
+    assert es <= GRAD_TOL and eu <= GRAD_TOL
