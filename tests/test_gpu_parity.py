@@ -7,7 +7,7 @@ import pytest
 import workloads as W
 from oracle.derivatives import StepDerivative, rollout_backward
 from oracle.step import rollout as orollout
-from tests.parity import GRAD_TOL, JAC_TOL, STATE_TOL, rel_l2, state_errors
+from tests.parity import GRAD_TOL, HARD_V_TOL, JAC_TOL, STATE_TOL, rel_l2, state_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -355,3 +355,33 @@ def test_cloth_48x48_forward_and_gradient():
     es, eu = rel_l2(s0b.cpu().numpy(), sb_ref), rel_l2(ub.cpu().numpy(), ub_ref)
     print(f"cloth 48x48: s0_bar err {es:.2e} u_bar err {eu:.2e}", flush=True)
     assert es <= GRAD_TOL and eu <= GRAD_TOL
+
+
+def test_hard_contact_forward_and_surrogate_gradient():
+    """Surrogate mode: hard contact (kappa_fwd = 0) drives the rollout and the
+    gradient uses kappa_bwd at the hard trajectory's states.  C1 (the rope
+    lands on the ground and drapes over the sphere) and a small rope batch."""
+    import torch
+    c1 = W.config_c1()
+    insts = [c1.replace(kappa_fwd=0.0)] + [i.replace(kappa_fwd=0.0) for i in W.small_rope_batch(2, 30, 20, seed=491)]
+    sim, s0, u, traj, st = _run(insts)
+    print("status", st, flush=True)
+    assert (st == 0).all()
+    parts = sim.split(traj, "traj")
+    for i, inst in enumerate(insts):
+        ref, rst = orollout(inst)
+        assert rst.max() == 0
+        ex, ev = state_errors(parts[i], ref, inst.n)
+        print(f"hard rope {i} n={inst.n} T={inst.T}: state err x {ex:.2e} v {ev:.2e}", flush=True)
+        assert ex <= STATE_TOL and ev <= HARD_V_TOL
+    rng = np.random.default_rng(17)
+    cot = [rng.normal(size=i.n_s) for i in insts]
+    s0b, ub = sim.backward(u, traj, sT_bar=sim.pack_states(cot))
+    torch.cuda.synchronize()
+    sp, up, tp = sim.split(s0b, "s"), sim.split(ub, "u"), sim.split(traj, "traj")
+    for i, inst in enumerate(insts):
+        tr = tp[i].reshape(inst.T + 1, inst.n_s).astype(np.float64)
+        sb_ref, ub_ref = rollout_backward(inst, tr, sT_bar=cot[i])
+        es, eu = rel_l2(sp[i], sb_ref), rel_l2(up[i], ub_ref)
+        print(f"hard rope {i} n={inst.n}: s0_bar err {es:.2e} u_bar err {eu:.2e}", flush=True)
+        assert es <= GRAD_TOL and eu <= GRAD_TOL
