@@ -319,7 +319,7 @@ def bench_c5(args, rates=(200.0, 15.0), quiet=False):
         duration = args.serve_seconds if rate >= 100 else max(4.0, 4 * args.serve_seconds)
         trace = W.serve_trace(rate, duration)
         res = {"offered_req_s": rate, "duration_s": duration, "requests": len(trace)}
-        for name, slots in (("batched", 8), ("plain", 1)):
+        for name, slots in (("batched", args.slots), ("plain", 1)):
             res[name] = _serve_once(trace, slots)
             if not quiet:
                 print(rate, name, res[name], file=sys.stderr, flush=True)
@@ -344,6 +344,7 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "probe", "copy"])
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--slots", type=int, default=8, help="device slots of the batched planning server")
     ap.add_argument("--no-serve", action="store_true", help="skip the short planning-stream leg")
     args = ap.parse_args()
     if args.gpus != 1:

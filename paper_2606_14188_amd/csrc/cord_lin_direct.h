@@ -391,10 +391,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
             for (int u = 0; u < kRing; ++u) w[u] = 0.f;
             auto row = [&](const int i, const int u, const bool guard) {
                 if (guard && i >= N) return;
+                // column-local right-hand side, without branches: both loads
+                // are unconditional (in-bounds clamped indices) so the rows
+                // of a block stay one basic block
                 const int dd = i - j;
                 const int ddc = min(max(dd, -kBand), kBand);
-                const float h = HB[ddc >= 0 ? i * 9 + ddc : j * 9 - ddc];
-                const float in = (dd == ddc) ? RF[i] : 0.f;
+                const int hidx = j * 9 - ddc + (ddc >= 0 ? 1 : 0) * (dd * 9 + 2 * ddc);   // H(max, min) in HB
+                const float h = HB[hidx];
+                const float rfi = RF[i];
+                const float in = (dd == ddc) ? rfi : 0.f;
                 float acc = -in * (h - (dd == 0 ? mdt2 : 0.f));
 #pragma unroll
                 for (int m = kBand; m >= 1; --m)
@@ -443,10 +448,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
                 // column-local part: G(m, j) - (H(m, j) - mdt2 d_mj) - [j free, same particle] NLN(m, j)
                 const int dq = j - mrow;
                 const int dqc = min(max(dq, -kBand), kBand), dgc = min(max(dq, -kGB), kGB);
-                const float hv = HB[dqc <= 0 ? mrow * 9 - dqc : j * 9 + dqc];
+                const int hidx = mrow * 9 - dqc + (dqc > 0 ? 1 : 0) * (dq * 9 + 2 * dqc);   // H(max, min) in HB
+                const float hv = HB[hidx];
                 const float gv = GB[mrow * 12 + kGB + dgc];
                 const float same = ((mrow / 3) == pj) ? lane_fj : 0.f;
-                const float nv = NL[mrow * 3 + cj] * same;
+                const float nl = NL[mrow * 3 + cj];
+                const float nv = nl * same;
                 const float in8 = (dq == dqc) ? 1.f : 0.f, in5 = (dq == dgc) ? 1.f : 0.f;
                 float r = in8 * (in5 * gv - nv - (hv - (dq == 0 ? mdt2 : 0.f)));
                 // G(m, m-5..m+5) eps; e[(u - qq)] holds eps_{mrow - 5 + qq}
