@@ -102,6 +102,8 @@ def bench_c3(args):
     from paper_2606_14188_amd import Sim, _lib as L
     insts = W.config_c3()
     sim = Sim(insts)
+    if not args.no_aux:
+        sim.use_aux(True)      # the full rollout keeps its step internals for the JVPs
     B, n, T = len(insts), insts[0].n, insts[0].T
     s0 = sim.pack_states([i.s0 for i in insts])
     u = sim.pack_controls([i.u for i in insts])
@@ -148,6 +150,8 @@ def bench_c4(args):
     from paper_2606_14188_amd import Sim, _lib as L
     insts = W.config_c4()
     sim = Sim(insts)
+    if not args.no_aux:
+        sim.use_aux(True)
     s0 = sim.pack_states([i.s0 for i in insts])
     u = sim.pack_controls([i.u for i in insts])
     sT = sim.pack_states([W.random_cotangent(i.n_s, 9000 + j) for j, i in enumerate(insts)])
@@ -345,6 +349,10 @@ def main():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--slots", type=int, default=8, help="device slots of the batched planning server")
+    ap.add_argument("--no-aux", action="store_true",
+                    help="re-solve every step in the adjoint and linearize instead of keeping the step internals")
+    ap.add_argument("--grasp", default="dirichlet", choices=["dirichlet", "penalty"],
+                    help="grasp of the rope batch (penalty: holonomic penalty with smoothed activation)")
     ap.add_argument("--no-serve", action="store_true", help="skip the short planning-stream leg")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -377,8 +385,13 @@ def main():
     from paper_2606_14188_amd import Sim
 
     insts = workload()
+    if args.grasp == "penalty":
+        import workloads as W
+        insts = [W.penalty_grasp(inst, seed=i) for i, inst in enumerate(insts)]
     B, n, T = len(insts), insts[0].n, insts[0].T
     sim = Sim(insts)
+    if not args.no_aux:
+        sim.use_aux(True)      # the adjoint and linearize reuse the rollout's step internals
     dev = sim.device
     s0 = sim.pack_states([i.s0 for i in insts])
     u = sim.pack_controls([i.u for i in insts])
@@ -452,7 +465,7 @@ def main():
     dom = max(kernels, key=lambda k: kern_ms[k])
     roof = dict(kernels[dom])
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = profiled_traffic(dom)
+    roof["traffic"] = profiled_traffic(dom) if args.grasp == "dirichlet" else None
     roof["kernel"] = dom
     serve = None
     if not args.no_serve:
@@ -473,7 +486,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "rope-64 x 1024, T=100, dt=0.005, 3 spheres + ground: forward + adjoint"
-                               + (" + dense A_t/B_t" if with_lin else ""),
+                               + (" + dense A_t/B_t" if with_lin else "")
+                               + (", penalty grasp" if args.grasp == "penalty" else ""),
                    "batch": B, "nodes": n, "horizon": T},
         "kernel_ms": kern_ms,
         "kernel_roofline": {k: dict(v, frac=v["achieved"] / v["peak"]) for k, v in kernels.items()},

@@ -170,7 +170,7 @@ typedef struct cord_sim cord_sim;
  * kappa_bwd <= 0 or kappa_fwd < 0, mass <= 0, h <= 0, negative stiffness),
  * CORD_EUNSUPPORTED (mu != 0, more than CORD_MAX_OBST obstacles, a node
  * count no kernel configuration covers: ropes up to 256 nodes, cloths up
- * to 1024 nodes), CORD_ENOMEM, CORD_EHIP.  *out is set only on success.
+ * to 2304 nodes), CORD_ENOMEM, CORD_EHIP.  *out is set only on success.
  */
 int cord_sim_create(const cord_instance_desc* inst, int32_t n_inst, cord_sim** out);
 
@@ -188,9 +188,33 @@ typedef struct {
     int64_t B_floats;      /* sum T n_s n_u     : dense B_t                */
     int32_t max_n;         /* largest node count                          */
     int32_t max_T;         /* longest horizon                             */
+    int64_t aux_floats;    /* sum 14 T n        : step internals (cord_sim_set_aux) */
 } cord_sim_info_t;
 
 int cord_sim_info(const cord_sim* sim, cord_sim_info_t* out);
+
+/*
+ * Keep the internals of every solved step so the derivatives need not
+ * re-solve it.  The adjoint and the linearizations of eq. (diff-sim) are
+ * evaluated at the step's stage-1 solution q*, its stage-2 correction and
+ * contact multipliers (Sec. 4.1, "Differentiating Through Simulation");
+ * without them each step is solved again from its stored state.
+ *   aux  device buffer of info.aux_floats floats, owned by the caller, or
+ *        NULL to stop using one.  Per instance and step: the stage-1
+ *        increment q* - x and the stage-2 correction (3 floats per node
+ *        each) and, per obstacle slot, the contact multiplier and gap.
+ * While a buffer is set, cord_rollout with FULL storage writes the
+ * internals of every step, and cord_rollout_backward with FULL storage and
+ * cord_linearize read them instead of solving the step again.  This applies
+ * to instances with kappa_fwd == kappa_bwd (the others are always solved
+ * again).  The caller must pass to cord_rollout_backward / cord_linearize
+ * the trajectory written by the last such rollout.  The derivatives are
+ * then evaluated at exactly the state the rollout solved; without the
+ * buffer the step is solved again (in the adjoint kernel with the same
+ * arithmetic, in the linearization kernels up to FP32 rounding).
+ * Errors: CORD_EINVAL (NULL sim).
+ */
+int cord_sim_set_aux(cord_sim* sim, float* aux);
 
 /*
  * Float offsets of every instance's block (host arrays of n_inst + 1

@@ -47,7 +47,7 @@ class InstanceDesc(ctypes.Structure):
 class SimInfo(ctypes.Structure):
     _fields_ = [("n_inst", c_int64), ("s_floats", c_int64), ("u_floats", c_int64),
                 ("traj_floats", c_int64), ("A_floats", c_int64), ("B_floats", c_int64),
-                ("max_n", c_int32), ("max_T", c_int32)]
+                ("max_n", c_int32), ("max_T", c_int32), ("aux_floats", c_int64)]
 
 
 class RolloutOpts(ctypes.Structure):
@@ -94,6 +94,7 @@ _EXPORTS = {
                                  c_void_p, c_void_p]),
     "cord_abi_sizes": (c_int32, [POINTER(c_int64), c_int32]),
     "cord_sim_set_launch": (c_int32, [c_void_p, c_int32]),
+    "cord_sim_set_aux": (c_int32, [c_void_p, c_void_p]),
     "cord_autotune": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_char_p, c_void_p]),
     "cord_sim_classes": (c_int32, [c_void_p] + [POINTER(c_int32)] * 5 + [c_int32, POINTER(c_int32)]),
     "cord_last_error": (c_char_p, []),

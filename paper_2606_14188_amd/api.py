@@ -165,6 +165,19 @@ class Sim:
                                         _ptr(status), _stream()))
         return (A if dense else None), (Bm if want_B else None), out
 
+    # ------------------------------------------------------------ step internals
+    def use_aux(self, on: bool = True):
+        """Keep the internals of every solved step (cord_sim_set_aux): FULL
+        rollouts write them, backward (FULL) and linearize read them instead
+        of solving each step again.  The buffer is owned by this object."""
+        if on:
+            if getattr(self, "_aux", None) is None:
+                self._aux = self._empty(max(self.info.aux_floats, 1))
+            L.check(self.lib.cord_sim_set_aux(self._h, _ptr(self._aux)))
+        else:
+            L.check(self.lib.cord_sim_set_aux(self._h, None))
+            self._aux = None
+
     # ------------------------------------------------------------ launch
     def set_launch(self, mode: int):
         """mode: _lib.LAUNCH_GROUPED / PER_INSTANCE / PERSISTENT / GRAPH."""

@@ -131,6 +131,7 @@ struct cord_sim {
     std::vector<hipEvent_t> join_ev;
     std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
     std::vector<std::vector<uintptr_t>> graph_order;
+    float* aux = nullptr;               // step internals (cord_sim_set_aux), caller-owned
 };
 
 namespace cord {
@@ -334,7 +335,8 @@ std::vector<uintptr_t> graph_key(int op, const KArgs& a) {
     return {(uintptr_t)op, (uintptr_t)a.s0, (uintptr_t)a.u, (uintptr_t)a.traj, (uintptr_t)a.final_out,
             (uintptr_t)a.traj_in, (uintptr_t)a.traj_bar, (uintptr_t)a.sT_bar, (uintptr_t)a.s0_bar,
             (uintptr_t)a.u_bar, (uintptr_t)a.status, (uintptr_t)a.counters, (uintptr_t)a.store,
-            (uintptr_t)a.ckpt_every, (uintptr_t)a.use_kappa_bwd, (uintptr_t)a.seg};
+            (uintptr_t)a.ckpt_every, (uintptr_t)a.use_kappa_bwd, (uintptr_t)a.seg, (uintptr_t)a.aux,
+            (uintptr_t)a.aux_mode};
 }
 
 int launch_all(cord_sim* s, int op, KArgs a, hipStream_t st) {
@@ -465,7 +467,7 @@ int cord_sim_create(const cord_instance_desc* inst, int32_t n_inst, cord_sim** o
     s->desc.assign(inst, inst + n_inst);
     s->h.resize(n_inst);
     s->group_of.assign(n_inst, -1);
-    int64_t so = 0, uo = 0, to = 0, tns = 0, ao = 0, bo = 0;
+    int64_t so = 0, uo = 0, to = 0, tns = 0, ao = 0, bo = 0, xo = 0;
     int max_n = 0, max_T = 0;
     std::map<std::pair<int, int>, int> class_group;
     for (int i = 0; i < n_inst; ++i) {
@@ -473,6 +475,8 @@ int cord_sim_create(const cord_instance_desc* inst, int32_t n_inst, cord_sim** o
         InstDev& I = s->h[i];
         fill_instdev(d, I);
         I.s_off = so; I.u_off = uo; I.traj_off = to; I.tns_off = tns; I.A_off = ao; I.B_off = bo;
+        I.aux_off = xo;
+        xo += (int64_t)kAuxFields * I.T * I.n;
         so += I.n_s;
         uo += (int64_t)I.T * I.n_u;
         to += (int64_t)(I.T + 1) * I.n_s;
@@ -499,7 +503,7 @@ int cord_sim_create(const cord_instance_desc* inst, int32_t n_inst, cord_sim** o
     }
     s->info.n_inst = n_inst;
     s->info.s_floats = so; s->info.u_floats = uo; s->info.traj_floats = to;
-    s->info.A_floats = ao; s->info.B_floats = bo;
+    s->info.A_floats = ao; s->info.B_floats = bo; s->info.aux_floats = xo;
     s->info.max_n = max_n; s->info.max_T = max_T;
     auto cleanup = [&](int code, const std::string& what) {
         cord_sim_destroy(s);
@@ -617,7 +621,15 @@ int cord_rollout(cord_sim* s, const float* s0, const float* u, float* traj, int3
     }
     a.s0 = s0; a.u = u; a.traj = traj; a.status = inst_status; a.counters = o.counters;
     a.final_out = o.final_state;
+    if (s->aux && o.store == CORD_STORE_FULL) { a.aux = s->aux; a.aux_mode = 1; }
     return launch_all(s, kOpRollout, a, (hipStream_t)stream);
+}
+
+int cord_sim_set_aux(cord_sim* s, float* aux) {
+    g_err.clear();
+    if (!s) return fail(CORD_EINVAL, "cord_sim_set_aux: NULL sim");
+    s->aux = aux;
+    return CORD_OK;
 }
 
 int cord_rollout_backward(cord_sim* s, const float* u, const float* traj, const float* traj_bar, float* s0_bar,
@@ -646,6 +658,7 @@ int cord_rollout_backward(cord_sim* s, const float* u, const float* traj, const 
     }
     a.u = u; a.traj_in = traj; a.traj_bar = traj_bar; a.sT_bar = o.sT_bar;
     a.s0_bar = s0_bar; a.u_bar = u_bar; a.status = inst_status; a.counters = o.counters;
+    if (s->aux && o.store == CORD_STORE_FULL) { a.aux = s->aux; a.aux_mode = 2; }
     return launch_all(s, kOpBackward, a, (hipStream_t)stream);
 }
 
@@ -658,6 +671,7 @@ int cord_linearize(cord_sim* s, const float* traj, const float* u, float* A, flo
     if (jvp && (jvp->k < 1 || !jvp->out)) return fail(CORD_EINVAL, "cord_linearize: jvp needs k >= 1 and out");
     KArgs a = base_args(s);
     a.traj_in = traj; a.u = u; a.A = A; a.Bm = Bm; a.status = inst_status;
+    if (s->aux) { a.aux = s->aux; a.aux_mode = 2; }
     if (jvp) { a.jvp_k = jvp->k; a.jvp_ds = jvp->ds; a.jvp_du = jvp->du; a.jvp_out = jvp->out; }
     hipStream_t st = (hipStream_t)stream;
     if (inst_status) CORD_HIP(launch_fill_i32(inst_status, s->info.n_inst, 0, st));

@@ -33,7 +33,12 @@ struct alignas(16) InstDev {
     int64_t tns_off;    // sum T n_s   (JVP blocks are k * this)
     int64_t A_off;      // sum T n_s^2
     int64_t B_off;      // sum T n_s n_u
+    int64_t aux_off;    // sum kAuxFields T n (step internals)
 };
+
+// Step internals kept per node and step: q* - x (3), the stage-2 correction
+// (3), the contact multiplier and gap of each obstacle slot.
+constexpr int kAuxFields = 6 + 2 * kMaxObs;
 
 // Kernel arguments shared by the three kernels.
 struct KArgs {
@@ -65,6 +70,8 @@ struct KArgs {
     uint32_t* counters;
     int32_t* queue;            // persistent launch: work-queue counter (zeroed before launch), or null
     int32_t lin_zero_off;      // linearize: write A/B at offset 0 (single-instance outputs)
+    float* aux;                // step internals, or null
+    int32_t aux_mode;          // 1: rollout writes them; 2: backward / linearize read them
 };
 
 }  // namespace cord

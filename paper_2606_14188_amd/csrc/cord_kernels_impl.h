@@ -35,8 +35,10 @@ __global__ __launch_bounds__(NT) void rollout_kernel(KArgs a) {
         const int T = I.T, ns = I.n_s, K = a.ckpt_every;
         if (a.store == CORD_STORE_FULL) S.store_state(a.traj + I.traj_off);
         else if (a.store == CORD_STORE_CKPT) S.store_state(a.traj + a.ckpt_off[id]);
+        const bool keep = a.aux_mode == 1 && I.kappa_fwd == I.kappa_bwd && a.store == CORD_STORE_FULL;
         for (int t = 0; t < T; ++t) {
             S.solve_step(a.u + I.u_off + (int64_t)t * I.n_u, kappa);
+            if (keep) S.save_aux(a.aux + I.aux_off + (int64_t)t * kAuxFields * I.n);
             S.advance();
             if (a.store == CORD_STORE_FULL) {
                 S.store_state(a.traj + I.traj_off + (int64_t)(t + 1) * ns);
@@ -74,7 +76,10 @@ template <int TOPO, int NT, int PPT, int NOBS>
 __device__ __forceinline__ void adjoint_step(Solver<TOPO, NT, PPT, NOBS>& S, const KArgs& a, const InstDev& I, int t,
                                              float xb[PPT][3], float vb[PPT][3], float ub[PPT][3]) {
     const int nu = I.n_u;
-    S.solve_step(a.u + I.u_off + (int64_t)t * nu, I.kappa_bwd);
+    if (a.aux_mode == 2 && I.kappa_fwd == I.kappa_bwd && a.store == CORD_STORE_FULL)
+        S.restore_step(a.u + I.u_off + (int64_t)t * nu, a.aux + I.aux_off + (int64_t)t * kAuxFields * I.n);
+    else
+        S.solve_step(a.u + I.u_off + (int64_t)t * nu, I.kappa_bwd);
     float dxb[PPT][3];
     S.adjoint(xb, vb, ub, I.kappa_bwd, dxb);
 #pragma unroll
@@ -170,7 +175,10 @@ __global__ __launch_bounds__(NT) void linearize_kernel(KArgs a) {
     const int n = I.n, ns = I.n_s, nu = I.n_u;
     const float kb = I.kappa_bwd, dt = I.dt, idt = 1.0f / I.dt;
     S.load_state(a.traj_in + I.traj_off + (int64_t)t * ns);
-    S.solve_step(a.u + I.u_off + (int64_t)t * nu, kb);
+    if (a.aux_mode == 2 && I.kappa_fwd == I.kappa_bwd)
+        S.restore_step(a.u + I.u_off + (int64_t)t * nu, a.aux + I.aux_off + (int64_t)t * kAuxFields * n);
+    else
+        S.solve_step(a.u + I.u_off + (int64_t)t * nu, kb);
 
     if (a.A || a.Bm) {
         const int64_t aoff = a.lin_zero_off ? 0 : I.A_off, boff = a.lin_zero_off ? 0 : I.B_off;

@@ -135,7 +135,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
     const int n = I.n, ns = I.n_s, nu = I.n_u, N = 3 * n;
     const float kap = I.kappa_bwd, dt = I.dt, idt = 1.0f / I.dt, gam = I.gamma, mdt2 = S.mdt2;
     S.load_state(a.traj_in + I.traj_off + (int64_t)t * ns);
-    S.solve_step(a.u + I.u_off + (int64_t)t * nu, kap);
+    if (a.aux_mode == 2 && I.kappa_fwd == I.kappa_bwd)
+        S.restore_step(a.u + I.u_off + (int64_t)t * nu, a.aux + I.aux_off + (int64_t)t * kAuxFields * n);
+    else
+        S.solve_step(a.u + I.u_off + (int64_t)t * nu, kap);
 
     float* B = lds + lds_floats<NT, 1>();
     float* LC = B + LL::LC;

@@ -113,6 +113,7 @@ struct Req {
     int32_t *d_ids = nullptr, *d_status = nullptr, *d_best = nullptr, *d_simst = nullptr;
     float *d_s0 = nullptr, *d_u = nullptr, *d_traj = nullptr, *d_sT = nullptr, *d_s0b = nullptr, *d_ub = nullptr;
     float *d_cost = nullptr, *d_bcost = nullptr, *d_ubest = nullptr, *d_tbest = nullptr, *d_A = nullptr, *d_B = nullptr;
+    float* d_aux = nullptr;   // step internals of the candidates' rollouts
     // results
     cord_plan_result res{};
     std::vector<float> h_u, h_traj, h_A, h_B, h_costs;
@@ -120,8 +121,9 @@ struct Req {
 
 size_t al(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
-size_t footprint_of(int C, int T, int ns, int nu, bool ab) {
+size_t footprint_of(int C, int T, int n, int ns, int nu, bool ab) {
     size_t f = 0;
+    f += al(4ull * C * T * n * kAuxFields);        // step internals
     f += al(sizeof(InstDev) * C) + al(4 * C) * 3 + al(8) * 2;
     f += al(4ull * C * ns) * 3;                     // s0, sT_bar, s0_bar
     f += al(4ull * C * T * nu) * 2;                 // u, u_bar
@@ -258,6 +260,7 @@ bool carve_all(cord_server* s, Req* q) {
     q->d_u = carve<float>(s, q, 4ull * C * T * nu);
     q->d_ub = carve<float>(s, q, 4ull * C * T * nu);
     q->d_traj = carve<float>(s, q, 4ull * C * (T + 1) * ns);
+    q->d_aux = carve<float>(s, q, 4ull * C * T * q->n * kAuxFields);
     q->d_cost = carve<float>(s, q, 4ull * C);
     q->d_bcost = q->d_cost ? carve<float>(s, q, 8) : nullptr;
     q->d_ubest = carve<float>(s, q, 4ull * T * nu);
@@ -268,7 +271,7 @@ bool carve_all(cord_server* s, Req* q) {
     }
     if (!q->d_inst || !q->d_ids || !q->d_status || !q->d_best || !q->d_simst || !q->d_s0 || !q->d_sT ||
         !q->d_s0b || !q->d_u || !q->d_ub || !q->d_traj || !q->d_cost || !q->d_bcost || !q->d_ubest ||
-        !q->d_tbest || (ab && (!q->d_A || !q->d_B))) {
+        !q->d_tbest || !q->d_aux || (ab && (!q->d_A || !q->d_B))) {
         for (auto& b : q->blocks) s->arena.release(b.first, b.second);
         q->blocks.clear();
         return false;
@@ -299,6 +302,7 @@ bool enqueue(cord_server* s, Req* q) {
         inst[c].tns_off = (int64_t)c * T * ns;
         inst[c].A_off = 0;
         inst[c].B_off = 0;
+        inst[c].aux_off = (int64_t)c * T * q->n * kAuxFields;
     }
     int32_t* ids = reinterpret_cast<int32_t*>(sg.up + U.ids);
     for (int c = 0; c < C; ++c) ids[c] = c;
@@ -340,17 +344,20 @@ bool enqueue(cord_server* s, Req* q) {
         KArgs f = a;
         f.store = CORD_STORE_FULL;
         f.s0 = q->d_s0; f.u = q->d_u; f.traj = q->d_traj;
+        f.aux = q->d_aux; f.aux_mode = 1;
         SRV_HIP(K.rollout(f, C, st));
         SRV_HIP(plan_cost(q->d_inst, C, q->d_traj, q->d_u, q->r.goal_node, q->r.goal, reg, q->d_cost, q->d_sT, st));
         KArgs b = a;
         b.store = CORD_STORE_FULL;
         b.u = q->d_u; b.traj_in = q->d_traj; b.sT_bar = q->d_sT; b.s0_bar = q->d_s0b; b.u_bar = q->d_ub;
+        b.aux = q->d_aux; b.aux_mode = 2;
         SRV_HIP(K.backward(b, C, st));
         SRV_HIP(plan_update(q->d_u, q->d_ub, (int64_t)C * T * nu, q->r.step, reg, q->r.u_max, st));
     }
     KArgs f = a;
     f.store = CORD_STORE_FULL;
     f.s0 = q->d_s0; f.u = q->d_u; f.traj = q->d_traj;
+    f.aux = q->d_aux; f.aux_mode = 1;
     SRV_HIP(K.rollout(f, C, st));
     SRV_HIP(plan_cost(q->d_inst, C, q->d_traj, q->d_u, q->r.goal_node, q->r.goal, reg, q->d_cost, nullptr, st));
     SRV_HIP(plan_argmin(q->d_cost, C, q->d_best, q->d_bcost, st));
@@ -364,6 +371,7 @@ bool enqueue(cord_server* s, Req* q) {
         l.traj_in = q->d_traj; l.u = q->d_u; l.A = q->d_A; l.Bm = q->d_B;
         l.lin_zero_off = 1;
         l.status = nullptr;
+        l.aux = q->d_aux; l.aux_mode = 2;
         const int topo = q->r.inst.kind == CORD_ROPE ? kRope : kCloth;
         SRV_HIP(launch_linearize(q->cfg, topo, bucket_of(topo, q->n), q->r.inst.grip_mode == CORD_GRIP_PENALTY, l, 1,
                                  T, st));
@@ -566,7 +574,7 @@ int cord_plan_submit(cord_server* s, const cord_plan_request* r, uint64_t* ticke
     q->C = r->n_cand;
     const int topo = d.kind == CORD_ROPE ? kRope : kCloth;
     q->cfg = default_config(topo, bucket_of(topo, n));
-    q->footprint = footprint_of(q->C, q->T, q->ns, q->nu, r->want_AB != 0);
+    q->footprint = footprint_of(q->C, q->T, q->n, q->ns, q->nu, r->want_AB != 0);
     q->s0.assign(r->s0, r->s0 + q->ns);
     if (r->u_warm) q->u_warm.assign(r->u_warm, r->u_warm + (size_t)q->T * q->nu);
     if (r->u_init) q->u_init.assign(r->u_init, r->u_init + (size_t)q->C * q->T * q->nu);

@@ -926,6 +926,56 @@ struct Solver {
         if (!conv) status = max(status, kStQP);
     }
 
+    // -------------------------------------------------- step internals
+    // Field-major per step: a[f * n + p], f < kAuxFields: q* - x (0..2), the
+    // stage-2 correction (3..5), contact multipliers (6..), gaps (6 + kMaxObs..).
+    __device__ __forceinline__ void save_aux(float* a) const {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int p = pidx(k);
+            if (!active(k)) continue;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { a[c * n + p] = d[k][c]; a[(3 + c) * n + p] = dl[k][c]; }
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) {
+                a[(6 + o) * n + p] = clam[k][o];
+                a[(6 + kMaxObs + o) * n + p] = cgap[k][o];
+            }
+        }
+    }
+    // The state of a solved step from its saved internals: the same
+    // registers and LDS mirrors solve_step leaves (same inputs, same
+    // arithmetic for the spring and contact data), without solving.
+    __device__ __forceinline__ void restore_step(const float* ut, const float* a) {
+        begin_step(ut);                    // grippers, predictor, penalty data; publishes X
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int p = pidx(k);
+            if (!isfree(k)) continue;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) d[k][c] = a[c * n + p];
+            put(D, k, d[k]);
+        }
+        sync();
+        float F[PPT][3];
+        grad_cache(false, F);              // exact Hessian data at y*
+        eval_contacts();
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int p = pidx(k);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dl[k][c] = isfree(k) ? a[(3 + c) * n + p] : 0.f;
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) {
+                const bool valid = o < nobs && isfree(k);
+                clam[k][o] = valid ? a[(6 + o) * n + p] : 0.f;
+                cgap[k][o] = valid ? a[(6 + kMaxObs + o) * n + p] : 1.f;
+            }
+        }
+        publish(DL, dl);
+        ++cnt[3];
+    }
+
     // Full step at relaxation kappa: stages 1 and 2 (state not advanced).
     __device__ __forceinline__ void solve_step(const float* ut, float kappa) {
         begin_step(ut);

@@ -385,3 +385,52 @@ def test_hard_contact_forward_and_surrogate_gradient():
         es, eu = rel_l2(sp[i], sb_ref), rel_l2(up[i], ub_ref)
         print(f"hard rope {i} n={inst.n}: s0_bar err {es:.2e} u_bar err {eu:.2e}", flush=True)
         assert es <= GRAD_TOL and eu <= GRAD_TOL
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_step_internals_bitwise(graph):
+    """With the step-internals buffer the adjoint and the linearizations
+    skip re-solving each step.  Batch: ropes of the direct-linearization classes and of the
+    iterative one, a cloth, a penalty-grasp rope and a rope whose forward
+    and gradient relaxations differ (always re-solved)."""
+    import torch
+    from paper_2606_14188_amd import Sim, _lib as L
+    insts = (W.small_rope_batch(1, 60, 6, seed=701) + W.small_rope_batch(1, 100, 5, seed=702)
+             + W.small_rope_batch(1, 200, 4, seed=703) + W.small_cloth_batch(1, 6, 5, 5, seed=704)
+             + [W.penalty_grasp(W.small_rope_batch(1, 30, 6, seed=705)[0], seed=3)])
+    r = W.small_rope_batch(1, 40, 5, seed=706)[0]
+    insts.append(r.replace(kappa_fwd=0.5 * r.kappa_bwd))
+    rng = np.random.default_rng(41)
+    cot = [rng.normal(size=i.n_s) for i in insts]
+    k = 2
+    ds = [rng.normal(size=(i.T, k, i.n_s)) for i in insts]
+    du = [rng.normal(size=(i.T, k, i.n_u)) for i in insts]
+    outs = []
+    for aux in (False, True):
+        sim = Sim(insts)
+        if graph:
+            sim.set_launch(L.LAUNCH_GRAPH)
+        if aux:
+            sim.use_aux(True)
+        s0 = sim.pack_states([i.s0 for i in insts])
+        u = sim.pack_controls([i.u for i in insts])
+        sT = sim.pack_states(cot)
+        st = torch.zeros(len(insts), dtype=torch.int32, device=sim.device)
+        traj = sim.rollout(s0, u, status=st)
+        s0b, ub = sim.backward(u, traj, sT_bar=sT)
+        A, Bm, jv = sim.linearize(traj, u, jvp_k=k, jvp_ds=sim.pack_states([d.ravel() for d in ds]),
+                                  jvp_du=sim.pack_states([d.ravel() for d in du]))
+        torch.cuda.synchronize()
+        assert (st.cpu().numpy() == 0).all()
+        outs.append([traj, s0b, ub, A, Bm, jv])
+    # the adjoint restores exactly the state the rollout solved (bitwise);
+    # a re-solve inside the linearization kernels repeats that arithmetic in
+    # another kernel (other reduction widths and contractions), so there the
+    # two paths agree to FP32 rounding
+    names = ["traj", "s0_bar", "u_bar"]
+    for nm, a, b in zip(names, outs[0][:3], outs[1][:3]):
+        assert torch.equal(a, b), nm
+    for nm, a, b in zip(["A", "B", "jvp"], outs[0][3:], outs[1][3:]):
+        e = (torch.linalg.norm(a - b) / torch.linalg.norm(a)).item()
+        print(f"{nm}: relative difference with / without step internals {e:.2e}", flush=True)
+        assert e <= 1e-5, nm
