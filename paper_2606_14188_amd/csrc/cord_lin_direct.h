@@ -43,10 +43,12 @@ namespace cord {
 constexpr int kBand = 8;   // half-bandwidth of H, K, J in scalar unknowns
 constexpr int kGB = 5;     // half-bandwidth of G = C - R - W
 constexpr int kRing = 24;  // rows per unrolled block of a sweep (ring size)
-constexpr int kPf = 12;    // rows of prefetch distance for the kept vector
+constexpr int kPf = 11;    // rows of prefetch distance for the kept vector
+constexpr int kPfR = 12;   // slots of the prefetch ring (divides kRing)
 // Interior blocks of sweep 2 start at a multiple of kRing >= 2 kBand, where
-// every band index they form lies inside the matrix.
-static_assert(kRing >= 2 * kBand && kPf < kRing, "ring too short for the sweep windows");
+// every band index they form lies inside the matrix.  A prefetched value
+// waits kPf rows in a ring of kPfR > kPf slots.
+static_assert(kRing >= 2 * kBand && kPf < kPfR && kRing % kPfR == 0, "ring too short for the sweep windows");
 
 // LDS carve-up (floats) for up to 3*NMAX rows.  HB and NL are written only
 // after the assembly has read the solver's LDS mirrors, so they reuse the
@@ -56,7 +58,7 @@ template <int NMAX>
 struct LinLds {
     static constexpr int N3 = 3 * NMAX;
     // inside the solver's region
-    static constexpr int HB = 0;                  // H(i, i-m), m = 0..8   [i][9]
+    static constexpr int HB = 0;                  // H_el(i, i-m), m = 0..8 [i][9] (H - M/dt^2 on free rows)
     static constexpr int NL = HB + N3 * 9;        // (w n n^T) row i, same-particle columns [i][3]
     static constexpr int SA = NL + N3 * 3;
     // after the solver's region
@@ -68,7 +70,36 @@ struct LinLds {
     static constexpr int GB = UR + N3 * 8;        // G(i, i-5+q), q = 0..10 [i][12]
     static constexpr int RF = GB + N3 * 12;       // 1 if row i is free
     static constexpr int TOTAL = RF + N3;
+    // B_t staging after sweep 2, over UR, GB and RF: 3 kMaxGrip columns and
+    // a sink of 2 N3 floats for the lanes of free particles
+    static_assert((3 * kMaxGrip + 2) * N3 <= TOTAL - UR, "B_t staging must fit in UR..RF");
 };
+
+// Raw buffer resource over one allocation (gfx9 descriptor: 32-bit data
+// format, no stride).  Loads whose lane offset lies past `bytes` return zero
+// without a memory access; the scalar offset is not range-checked, so the
+// callers keep it inside the allocation.
+struct BufRes {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ BufRes(const float* base, uint32_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, (int)bytes, 0x00020000)) {}
+    __device__ float ld(uint32_t voff, uint32_t soff) const {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    }
+    __device__ void st(float v, uint32_t voff, uint32_t soff) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+    }
+};
+
+// A wave-uniform row index copied into a VGPR.  LDS reads at "array + f(row)
+// + constant" then keep one vector base per array and put the constant in
+// the instruction's offset field; a base in a scalar register is instead
+// rebuilt and copied to a VGPR for every read.
+__device__ __forceinline__ int vrow(int x) {
+    int r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
 
 __device__ __forceinline__ void sym_to_full(const float s[6], float m[3][3]) {
     m[0][0] = s[0]; m[0][1] = s[1]; m[0][2] = s[2];
@@ -306,7 +337,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
                             kf = hf;
                         }
                     }
-                    HB[i * 9 + m] = hv;
+                    HB[i * 9 + m] = hv - ((m == 0 && fr) ? mdt2 : 0.f);   // H_el
                     if (m == 0) {
                         LI[i] = hf;
                         UD[N - 1 - i] = kf;
@@ -361,172 +392,225 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
     __syncthreads();
 
     // ---------------------------------------------------------- column sweeps
+    // Global accesses of the sweeps are raw buffer instructions over this
+    // step's A_t: a loop-invariant lane offset (VGPR) plus a wave-uniform row
+    // offset in bytes (SGPR).  LDS reads of a block of rows go through one
+    // base address per array and constant offsets.
     const int j = threadIdx.x;
     const bool jok = j < N;
-    if (a.A && jok) {
+    if (a.A) {
         const int64_t aoff = a.lin_zero_off ? 0 : I.A_off, boff = a.lin_zero_off ? 0 : I.B_off;
         float* At = a.A + aoff + (int64_t)t * ns * ns;
         float* Bt = a.Bm ? a.Bm + boff + (int64_t)t * ns * nu : nullptr;
-        float* Sv = At + (int64_t)N * ns + N + j;     // kept vector: column j of the dv+/dv block
+        const BufRes rA(At, (uint32_t)ns * (uint32_t)ns * 4u);
+        const uint32_t rs = (uint32_t)ns * 4u;                  // bytes per row of A_t
+        const uint32_t vJ = 4u * (uint32_t)j, vJN = 4u * (uint32_t)(N + j);
+        const uint32_t vNJ = (uint32_t)N * rs + vJ, vK = (uint32_t)N * rs + vJN;
+        // vK: the kept vector, column j of the dv+/dv block
         const int pj = j / 3, cj = j - 3 * pj;
-        const bool fj = RF[j] != 0.f;
-        int gj = -1;
-        for (int g = 0; g < I.n_grip; ++g)
-            if (I.grip_node[g] == pj) gj = g;
-        const int i0 = max(0, (int)(threadIdx.x & ~63) - kBand);
+        const bool fj = jok && RF[jok ? j : 0] != 0.f;
+        // first row that can be nonzero in w1 for any column of this
+        // wavefront (wave-uniform: kept in a scalar register)
+        const int i0 = __builtin_amdgcn_readfirstlane(max(0, (int)(threadIdx.x & ~63) - kBand));
 
         // Each sweep runs in blocks of kRing rows whose body is unrolled, so
         // the ring slot of a row (its position mod kRing) is a constant and
         // the rolling windows stay in registers.  Blocks that cannot reach
         // past either end of the matrix run a body without any condition
-        // (one basic block: the LDS band reads of all its rows can be issued
-        // ahead of the arithmetic); the first and last blocks run the
-        // guarded body.  Sums are taken from the oldest window entry to the
-        // newest, so each recurrence waits on one multiply-add per row.
-        const float lane_fj = fj ? 1.f : 0.f;
+        // (one basic block, so its LDS reads can be issued ahead of the
+        // arithmetic); the first and last blocks run the guarded body.  Sums
+        // are taken from the oldest window entry to the newest, so each
+        // recurrence waits on one multiply-add per row.  Band entries outside
+        // the band are read at clamped (valid) indices and zeroed by selects.
 
         // sweep 1: w1 = L^{-1} r1 for rows i0..N-1 (rows above i0 are zero
-        // for every column of this wavefront and are stored as zeros)
-        for (int i = 0; i < i0; ++i) Sv[(int64_t)i * ns] = 0.f;
-        {
+        // for every column of this wavefront and are not stored)
+        if (jok) {
             float w[kRing];
 #pragma unroll
             for (int u = 0; u < kRing; ++u) w[u] = 0.f;
-            auto row = [&](const int i, const int u, const bool guard) {
-                if (guard && i >= N) return;
-                // column-local right-hand side, without branches: both loads
-                // are unconditional (in-bounds clamped indices) so the rows
-                // of a block stay one basic block
-                const int dd = i - j;
-                const int ddc = min(max(dd, -kBand), kBand);
-                const int hidx = j * 9 - ddc + (ddc >= 0 ? 1 : 0) * (dd * 9 + 2 * ddc);   // H(max, min) in HB
-                const float h = HB[hidx];
-                const float rfi = RF[i];
-                const float in = (dd == ddc) ? rfi : 0.f;
-                float acc = -in * (h - (dd == 0 ? mdt2 : 0.f));
-#pragma unroll
-                for (int m = kBand; m >= 1; --m)
-                    if (!guard || i - m >= i0) acc -= LC[(i - m) * 8 + m - 1] * w[(u - m + kRing) % kRing];
-                const float wi = acc * LI[i];
-                w[u] = wi;
-                Sv[(int64_t)i * ns] = wi;
-            };
             for (int tb = 0; i0 + tb < N; tb += kRing) {
-                const bool plain = tb > 0 && i0 + tb + kRing <= N;
-                if (plain) {
+                const int r0 = i0 + tb;                         // row of u = 0
+                const float* LCb = lds + vrow((int)(LC - lds) + (r0 - kBand) * 8);   // L(i, i-m) at LCb[(u+kBand-m)*8 + m-1]
+                const float* LIb = lds + vrow((int)(LI - lds) + r0);
+                const float* RFb = lds + vrow((int)(RF - lds) + r0);
+                const int db = r0 - j;
+                const uint32_t so = (uint32_t)r0 * rs;
+                auto row = [&](const int u, const bool guard) {
+                    const int i = r0 + u;
+                    if (guard && i >= N) return;
+                    // -(H_el z)_f: H_el(max(i,j), min(i,j)) inside the band
+                    const int dd = db + u;
+                    const int ddc = min(max(dd, -kBand), kBand);
+                    const int hidx = 9 * j - ddc + (dd >= 0 ? 9 * dd + 2 * ddc : 0);
+                    const float h = HB[hidx];
+                    const float rfi = RFb[u];
+                    float acc = (dd == ddc) ? -rfi * h : 0.f;
 #pragma unroll
-                    for (int u = 0; u < kRing; ++u) row(i0 + tb + u, u, false);
+                    for (int m = kBand; m >= 1; --m)
+                        if (!guard || i - m >= i0) acc -= LCb[(u + kBand - m) * 8 + m - 1] * w[(u - m + kRing) % kRing];
+                    const float wi = acc * LIb[u];
+                    w[u] = wi;
+                    rA.st(wi, vK, so + (uint32_t)u * rs);
+                };
+                if (tb > 0 && r0 + kRing <= N) {
+#pragma unroll
+                    for (int u = 0; u < kRing; ++u) row(u, false);
                 } else {
 #pragma unroll
-                    for (int u = 0; u < kRing; ++u) row(i0 + tb + u, u, true);
+                    for (int u = 0; u < kRing; ++u) row(u, true);
                 }
             }
         }
         // sweep 2 (descending, position s = N-1-i): eps, r (kGB rows behind), w2
-        {
-            float e[kRing], w2[kRing], pf[kRing];
+        if (jok) {
+            // loads of w1 through a window that starts at row i0: rows above
+            // it fall outside the window (the lane offset wraps past its
+            // size) and read as zero without touching memory
+            const BufRes rK(At + (int64_t)(N + i0) * ns + N, (uint32_t)(N - i0) * rs);
+            const uint32_t vW = 4u * (uint32_t)j;
+            float e[kRing], w2[kRing], pf[kPfR];
 #pragma unroll
-            for (int u = 0; u < kRing; ++u) { e[u] = 0.f; w2[u] = 0.f; pf[u] = 0.f; }
+            for (int u = 0; u < kRing; ++u) { e[u] = 0.f; w2[u] = 0.f; }
 #pragma unroll
-            for (int u = 0; u < kPf; ++u) pf[u] = Sv[(int64_t)max(N - 1 - u, 0) * ns];
-            auto row = [&](const int sp, const int u, const bool guard) {
-                const int i = N - 1 - sp;
-                if (guard && sp >= N + kGB) return;
-                // prefetch the kept value kPf rows ahead (a clamped row is
-                // loaded but never used)
-                pf[(u + kPf) % kRing] = Sv[(int64_t)max(i - kPf, 0) * ns];
-                float ei = 0.f;
-                if (!guard || i >= 0) {
-                    const float4 l0 = *reinterpret_cast<const float4*>(LC + i * 8);
-                    const float4 l1 = *reinterpret_cast<const float4*>(LC + i * 8 + 4);
-                    const float lc[8] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
-                    float acc = pf[u];
+            for (int u = 0; u < kPfR; ++u) pf[u] = 0.f;
 #pragma unroll
-                    for (int m = kBand; m >= 1; --m) acc -= lc[m - 1] * e[(u - m + kRing) % kRing];
-                    ei = acc * LI[i];
-                }
-                e[u] = ei;
-                const int mrow = i + kGB;
-                if (guard && mrow >= N) { w2[u] = 0.f; return; }
-                // column-local part: G(m, j) - (H(m, j) - mdt2 d_mj) - [j free, same particle] NLN(m, j)
-                const int dq = j - mrow;
-                const int dqc = min(max(dq, -kBand), kBand), dgc = min(max(dq, -kGB), kGB);
-                const int hidx = mrow * 9 - dqc + (dqc > 0 ? 1 : 0) * (dq * 9 + 2 * dqc);   // H(max, min) in HB
-                const float hv = HB[hidx];
-                const float gv = GB[mrow * 12 + kGB + dgc];
-                const float same = ((mrow / 3) == pj) ? lane_fj : 0.f;
-                const float nl = NL[mrow * 3 + cj];
-                const float nv = nl * same;
-                const float in8 = (dq == dqc) ? 1.f : 0.f, in5 = (dq == dgc) ? 1.f : 0.f;
-                float r = in8 * (in5 * gv - nv - (hv - (dq == 0 ? mdt2 : 0.f)));
-                // G(m, m-5..m+5) eps; e[(u - qq)] holds eps_{mrow - 5 + qq}
-                const float4 g0 = *reinterpret_cast<const float4*>(GB + mrow * 12);
-                const float4 g1 = *reinterpret_cast<const float4*>(GB + mrow * 12 + 4);
-                const float4 g2 = *reinterpret_cast<const float4*>(GB + mrow * 12 + 8);
-                const float gr[12] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w, g2.x, g2.y, g2.z, g2.w};
-#pragma unroll
-                for (int qq = 2 * kGB; qq >= 0; --qq) r += gr[qq] * e[(u - qq + kRing) % kRing];
-                r *= RF[mrow];
-                const float4 q0 = *reinterpret_cast<const float4*>(UR + mrow * 8);
-                const float4 q1 = *reinterpret_cast<const float4*>(UR + mrow * 8 + 4);
-                const float ur[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
-                float pre = 0.f;
-#pragma unroll
-                for (int q = kBand; q >= 2; --q) pre += ur[q - 1] * w2[(u - q + kRing) % kRing];
-                const float acc = (r - pre) - ur[0] * w2[(u - 1 + kRing) % kRing];
-                const float wv = acc * UD[N - 1 - mrow];
-                w2[u] = wv;
-                Sv[(int64_t)mrow * ns] = wv;
-            };
+            for (int u = 0; u < kPf; ++u) pf[u] = rK.ld(vW + (uint32_t)(N - 1 - u - i0) * rs, 0);
             for (int sb = 0; sb < N + kGB; sb += kRing) {
-                const bool plain = sb >= kGB && sb + kRing <= N;
-                if (plain) {
+                // row of position sb+u is i = ib + v, v = kRing-1-u
+                const int ib = N - kRing - sb;
+                const int mb = ib + kGB;                        // mrow = mb + v
+                const float* LCb = lds + vrow((int)(LC - lds) + ib * 8);
+                const float* LIb = lds + vrow((int)(LI - lds) + ib);
+                const float* GBb = lds + vrow((int)(GB - lds) + mb * 12);
+                const float* URb = lds + vrow((int)(UR - lds) + mb * 8);
+                const float* RFb = lds + vrow((int)(RF - lds) + mb);
+                const float* NLb = NL + mb * 3 + cj;
+                const float* UDb = lds + vrow((int)(UD - lds) + sb - kGB);   // UD[N-1-mrow] = UDb[u]
+                const int qb = j - mb;                          // dq = j - mrow = qb - v
+                const uint32_t vpf = vW + (uint32_t)(ib - kPf - i0) * rs;   // row i-kPf = ib-kPf+v
+                const uint32_t som = (uint32_t)mb * rs;
+                auto row = [&](const int u, const bool guard) {
+                    const int v = kRing - 1 - u;
+                    const int sp = sb + u;
+                    const int i = ib + v;
+                    if (guard && sp >= N + kGB) return;
+                    // kept w1 kPf rows ahead
+                    pf[(u + kPf) % kPfR] = rK.ld(vpf + (uint32_t)v * rs, 0);
+                    float ei = 0.f;
+                    if (!guard || i >= 0) {
+                        const float4 l0 = *reinterpret_cast<const float4*>(LCb + v * 8);
+                        const float4 l1 = *reinterpret_cast<const float4*>(LCb + v * 8 + 4);
+                        const float lc[8] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
+                        float acc = pf[u % kPfR];
 #pragma unroll
-                    for (int u = 0; u < kRing; ++u) row(sb + u, u, false);
+                        for (int m = kBand; m >= 1; --m) acc -= lc[m - 1] * e[(u - m + kRing) % kRing];
+                        ei = acc * LIb[v];
+                    }
+                    e[u] = ei;
+                    if (guard && i + kGB >= N) { w2[u] = 0.f; return; }
+                    // column-local part: G(m, j) - H_el(m, j) - [same particle] NLN(m, j)
+                    // (a same-particle column of a free row is free)
+                    const int dq = qb - v;
+                    const int dqc = min(max(dq, -kBand), kBand), dgc = min(max(dq, -kGB), kGB);
+                    const int hidx = 9 * j + dqc - (dq <= 0 ? 9 * dq + 2 * dqc : 0);
+                    const float hv = HB[hidx];
+                    const float gv = GBb[v * 12 + kGB + dgc];
+                    const float nl = NLb[v * 3];
+                    const bool same = (uint32_t)(cj - dq) <= 2u;
+                    float r = ((dq == dgc) ? gv : 0.f) - (same ? nl : 0.f) - ((dq == dqc) ? hv : 0.f);
+                    // G(m, m-5..m+5) eps; e[(u - qq)] holds eps_{mrow - 5 + qq}
+                    const float4 g0 = *reinterpret_cast<const float4*>(GBb + v * 12);
+                    const float4 g1 = *reinterpret_cast<const float4*>(GBb + v * 12 + 4);
+                    const float4 g2 = *reinterpret_cast<const float4*>(GBb + v * 12 + 8);
+                    const float gr[12] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w, g2.x, g2.y, g2.z, g2.w};
+#pragma unroll
+                    for (int qq = 2 * kGB; qq >= 0; --qq) r += gr[qq] * e[(u - qq + kRing) % kRing];
+                    r *= RFb[v];
+                    const float4 q0 = *reinterpret_cast<const float4*>(URb + v * 8);
+                    const float4 q1 = *reinterpret_cast<const float4*>(URb + v * 8 + 4);
+                    const float ur[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+                    float pre = 0.f;
+#pragma unroll
+                    for (int q = kBand; q >= 2; --q) pre += ur[q - 1] * w2[(u - q + kRing) % kRing];
+                    const float acc = (r - pre) - ur[0] * w2[(u - 1 + kRing) % kRing];
+                    const float wv = acc * UDb[u];
+                    w2[u] = wv;
+                    rA.st(wv, vK, som + (uint32_t)v * rs);
+                };
+                if (sb >= kGB && sb + kRing <= N) {
+#pragma unroll
+                    for (int u = 0; u < kRing; ++u) row(u, false);
                 } else {
 #pragma unroll
-                    for (int u = 0; u < kRing; ++u) row(sb + u, u, true);
+                    for (int u = 0; u < kRing; ++u) row(u, true);
                 }
             }
         }
+        // UR, GB and RF are not read again: B_t columns are staged there
+        __syncthreads();
+        float* BS = B + LL::UR;                         // [3 kMaxGrip][N3]: column 3g+c of B_t
+        float* BD = BS + 3 * kMaxGrip * LL::N3;         // per-lane sink for columns that are not gripped
         // sweep 3 (ascending): E = U^{-T} w2 and the outputs
-        {
-            float E[kRing], pf[kRing];
+        if (jok) {
+            int gj = -1;
+            for (int g = 0; g < I.n_grip; ++g)
+                if (I.grip_node[g] == pj) gj = g;
+            float* const bsl = gj >= 0 ? BS + (3 * gj + cj) * LL::N3 : BD + j;
+            float E[kRing], pf[kPfR];
 #pragma unroll
-            for (int u = 0; u < kRing; ++u) { E[u] = 0.f; pf[u] = 0.f; }
+            for (int u = 0; u < kRing; ++u) E[u] = 0.f;
 #pragma unroll
-            for (int u = 0; u < kPf; ++u) pf[u] = Sv[(int64_t)min(u, N - 1) * ns];
+            for (int u = 0; u < kPfR; ++u) pf[u] = 0.f;
+#pragma unroll
+            for (int u = 0; u < kPf; ++u) pf[u] = rA.ld(vK, (uint32_t)min(u, N - 1) * rs);
             const float c1 = dt * (1.f - gam), omg = 1.f - gam;
             const float cv = fj ? c1 : 0.f, vv = fj ? omg : 0.f;
-            auto row = [&](const int i, const int u, const bool guard) {
-                if (guard && i >= N) return;
-                pf[(u + kPf) % kRing] = Sv[(int64_t)min(i + kPf, N - 1) * ns];
-                const float4 c0 = *reinterpret_cast<const float4*>(UW + (N - 1 - i) * 8);
-                const float4 c1v = *reinterpret_cast<const float4*>(UW + (N - 1 - i) * 8 + 4);
-                const float uc[8] = {c0.x, c0.y, c0.z, c0.w, c1v.x, c1v.y, c1v.z, c1v.w};
-                float acc = pf[u];
-#pragma unroll
-                for (int q = kBand; q >= 1; --q) acc -= uc[q - 1] * E[(u - q + kRing) % kRing];
-                const float Ei = acc * UD[N - 1 - i];
-                E[u] = Ei;
-                const float dx = (i == j ? 1.f : 0.f) + Ei;
-                At[(int64_t)i * ns + j] = dx;
-                At[(int64_t)(N + i) * ns + j] = Ei * idt;
-                At[(int64_t)i * ns + N + j] = cv * dx;
-                At[(int64_t)(N + i) * ns + N + j] = vv * dx;
-                if (Bt && gj >= 0) {
-                    Bt[(int64_t)i * nu + 3 * gj + cj] = dt * dx;
-                    Bt[(int64_t)(N + i) * nu + 3 * gj + cj] = dx;
-                }
-            };
             for (int tb = 0; tb < N; tb += kRing) {
-                if (tb + kRing <= N) {
+                // U(i-q, i) at UWb[(kRing-1-u)*8 + q-1], 1/U(i,i) at UDb[kRing-1-u]
+                const float* UWb = lds + vrow((int)(UW - lds) + (N - kRing - tb) * 8);
+                const float* UDb = lds + vrow((int)(UD - lds) + N - kRing - tb);
+                float* const bsb = bsl + tb;
+                const uint32_t so = (uint32_t)tb * rs;
+                auto row = [&](const int u, const bool guard) {
+                    const int i = tb + u;
+                    if (guard && i >= N) return;
+                    pf[(u + kPf) % kPfR] = rA.ld(vK, guard ? (uint32_t)min(i + kPf, N - 1) * rs
+                                                            : so + (uint32_t)(u + kPf) * rs);
+                    const float4 c0 = *reinterpret_cast<const float4*>(UWb + (kRing - 1 - u) * 8);
+                    const float4 c1v = *reinterpret_cast<const float4*>(UWb + (kRing - 1 - u) * 8 + 4);
+                    const float uc[8] = {c0.x, c0.y, c0.z, c0.w, c1v.x, c1v.y, c1v.z, c1v.w};
+                    float acc = pf[u % kPfR];
 #pragma unroll
-                    for (int u = 0; u < kRing; ++u) row(tb + u, u, false);
+                    for (int q = kBand; q >= 1; --q) acc -= uc[q - 1] * E[(u - q + kRing) % kRing];
+                    const float Ei = acc * UDb[kRing - 1 - u];
+                    E[u] = Ei;
+                    const float dx = (i == j ? 1.f : 0.f) + Ei;
+                    const uint32_t sr = so + (uint32_t)u * rs;
+                    rA.st(dx, vJ, sr);
+                    rA.st(Ei * idt, vNJ, sr);
+                    rA.st(cv * dx, vJN, sr);
+                    rA.st(vv * dx, vK, sr);
+                    bsb[u] = dx;
+                };
+                if (tb + kRing + kPf <= N) {
+#pragma unroll
+                    for (int u = 0; u < kRing; ++u) row(u, false);
                 } else {
 #pragma unroll
-                    for (int u = 0; u < kRing; ++u) row(tb + u, u, true);
+                    for (int u = 0; u < kRing; ++u) row(u, true);
                 }
+            }
+        }
+        // B_t: j gripped (node of gripper g, coordinate c) gives column 3g+c,
+        // B[i][3g+c] = dt (d_ij + E_i), B[3n+i][3g+c] = d_ij + E_i
+        if (Bt) {
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < N * nu; idx += NT) {
+                const int i = idx / nu, s = idx - i * nu;
+                const float v = BS[s * LL::N3 + i];
+                Bt[(int64_t)i * nu + s] = dt * v;
+                Bt[(int64_t)(N + i) * nu + s] = v;
             }
         }
     }
