@@ -17,6 +17,7 @@
 
 #include "../../include/cord.h"
 #include "cord_internal.h"
+#include "cord_host.h"
 #include "cord_kernels.h"
 
 using namespace cord;
@@ -57,26 +58,33 @@ const int kClothBuckets[] = {64, 128, 256, 512, 1024, 2304};
 // iterative kernel.
 // Setting CORD_LINEARIZE_ITERATIVE=1 in the environment forces the iterative
 // kernel everywhere (for comparisons).
-hipError_t launch_linearize(int cfg_index, int topo, int nmax, bool penalty, const KArgs& a, int nblk, int tmax,
-                            hipStream_t st) {
-    static const bool iterative = [] {
+namespace {
+bool use_iterative_only() {
+    static const bool it = [] {
         const char* e = std::getenv("CORD_LINEARIZE_ITERATIVE");
         return e && e[0] == '1';
     }();
+    return it;
+}
+}  // namespace
+
+hipError_t launch_linearize(int cfg_index, int topo, int nmax, bool penalty, const KArgs& a, int nblk, int tmax,
+                            hipStream_t st, const KeptSource& ks) {
     int count = 0;
     const KernelCfg* cfg = kernel_configs(&count);
-    if (a.A && topo == kRope && !penalty && !iterative) {
+    int wg = 0;
+    const size_t kf = (a.A && topo == kRope && !penalty && !use_iterative_only())
+                          ? linearize_rope_direct_scratch(nmax, &wg) : 0;
+    if (wg > 0) {
         KArgs ad = a;
         ad.jvp_k = 0; ad.jvp_ds = nullptr; ad.jvp_du = nullptr; ad.jvp_out = nullptr;
-        bool handled = false;
-        hipError_t e = linearize_rope_direct(nmax, ad, nblk, tmax, st, &handled);
-        if (e != hipSuccess) return e;
-        if (handled) {
-            if (!a.jvp_out) return hipSuccess;
-            KArgs aj = a;
-            aj.A = nullptr; aj.Bm = nullptr;
-            return cfg[cfg_index].linearize(aj, nblk, tmax, st);
-        }
+        ad.kept = ks.get(ks.ctx, kf);   // null: vectors kept inside A
+        ad.kept_tg = wg;
+        hipError_t e = linearize_rope_direct(nmax, ad, nblk, tmax, st);
+        if (e != hipSuccess || !a.jvp_out) return e;
+        KArgs aj = a;
+        aj.A = nullptr; aj.Bm = nullptr;
+        return cfg[cfg_index].linearize(aj, nblk, tmax, st);
     }
     return cfg[cfg_index].linearize(a, nblk, tmax, st);
 }
@@ -132,6 +140,8 @@ struct cord_sim {
     std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
     std::vector<std::vector<uintptr_t>> graph_order;
     float* aux = nullptr;               // step internals (cord_sim_set_aux), caller-owned
+    float* kept = nullptr;              // direct rope linearization scratch
+    size_t kept_floats = 0;
 };
 
 namespace cord {
@@ -280,6 +290,22 @@ int ensure_seg(cord_sim* s, int K) {
     s->seg_floats = (size_t)off[B];
     s->seg_K = K;
     return CORD_OK;
+}
+
+// Scratch table of the direct rope linearization, grown on demand (hipFree
+// waits for work still using the old buffer); null if it cannot be had.
+float* sim_kept(void* ctx, size_t floats) {
+    cord_sim* s = static_cast<cord_sim*>(ctx);
+    if (floats > s->kept_floats) {
+        if (s->kept) { (void)hipFree(s->kept); s->kept = nullptr; s->kept_floats = 0; }
+        if (hipMalloc(&s->kept, sizeof(float) * floats) != hipSuccess) {
+            (void)hipGetLastError();   // run without the scratch
+            s->kept = nullptr;
+            return nullptr;
+        }
+        s->kept_floats = floats;
+    }
+    return s->kept;
 }
 
 int ensure_streams(cord_sim* s) {
@@ -537,6 +563,7 @@ int cord_sim_destroy(cord_sim* s) {
     for (auto& kv : s->ckpt_dev) (void)hipFree(kv.second);
     if (s->seg) (void)hipFree(s->seg);
     if (s->seg_off) (void)hipFree(s->seg_off);
+    if (s->kept) (void)hipFree(s->kept);
     if (s->d_queues) (void)hipFree(s->d_queues);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
@@ -678,7 +705,7 @@ int cord_linearize(cord_sim* s, const float* traj, const float* u, float* A, flo
     for (const Group& g : s->groups) {
         a.ids = g.d_ids;
         a.n_ids = (int)g.ids.size();
-        CORD_HIP(launch_linearize(g.cfg, g.topo, g.nmax, g.penalty, a, a.n_ids, g.tmax, st));
+        CORD_HIP(launch_linearize(g.cfg, g.topo, g.nmax, g.penalty, a, a.n_ids, g.tmax, st, KeptSource{&sim_kept, s}));
     }
     return CORD_OK;
 }

@@ -11,6 +11,13 @@ int default_config(int topo, int nmax);
 int set_error(int code, const char* msg);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 struct KArgs;
+// Optional device scratch for a linearize launch: get(ctx, floats) returns a
+// buffer of at least that many floats that no other work uses until the
+// launch ends, or null (the kernel then works without it).
+struct KeptSource {
+    float* (*get)(void* ctx, size_t floats);
+    void* ctx;
+};
 hipError_t launch_linearize(int cfg_index, int topo, int nmax, bool penalty, const KArgs& a, int nblk, int tmax,
-                            hipStream_t st);
+                            hipStream_t st, const KeptSource& ks);
 }  // namespace cord

@@ -72,6 +72,8 @@ struct KArgs {
     int32_t lin_zero_off;      // linearize: write A/B at offset 0 (single-instance outputs)
     float* aux;                // step internals, or null
     int32_t aux_mode;          // 1: rollout writes them; 2: backward / linearize read them
+    float* kept;               // direct rope linearization: scratch slots, or null
+    int32_t kept_tg;           // workgroup slots per CU in that scratch table
 };
 
 }  // namespace cord

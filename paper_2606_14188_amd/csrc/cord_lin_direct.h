@@ -26,9 +26,15 @@
 //   3 (ascending)  E = U^{-T} w2, written out as the A_t (and B_t) columns.
 // Choosing U U^T for K makes its first triangular solve run in the same
 // direction as the second solve with L, so one vector per column (w1, then
-// w2 in its place) is all that must be kept between sweeps.  It is kept in
-// the column's own slot of the dv+/dv block of A_t, which sweep 3 overwrites
-// with the final value.  The band factors, J and the right-hand-side
+// w2 in its place) is all that must be kept between sweeps.  It is kept in a
+// scratch slot owned by the workgroup's hardware slot (XCD, shader engine,
+// CU, workgroup slot on the CU; [wavefront][row][lane], each wavefront's rows
+// one contiguous stream): workgroups resident at the same time never share a
+// slot, a slot is reused only on one XCD (one L2), and the kept data of all
+// resident workgroups is a small working set rewritten in place.  Without
+// scratch (or on a device whose hardware slot falls outside the table) the
+// vector is kept in the column's own slot of the dv+/dv block of A_t, which
+// sweep 3 overwrites last.  The band factors, J and the right-hand-side
 // stencils sit in LDS and are read at wave-uniform addresses (broadcast).
 //
 // Outputs for column j (dx+ rows first, then dv+ rows; d_ij = [i == j]):
@@ -42,13 +48,18 @@ namespace cord {
 
 constexpr int kBand = 8;   // half-bandwidth of H, K, J in scalar unknowns
 constexpr int kGB = 5;     // half-bandwidth of G = C - R - W
-constexpr int kRing = 24;  // rows per unrolled block of a sweep (ring size)
-constexpr int kPf = 11;    // rows of prefetch distance for the kept vector
-constexpr int kPfR = 12;   // slots of the prefetch ring (divides kRing)
-// Interior blocks of sweep 2 start at a multiple of kRing >= 2 kBand, where
-// every band index they form lies inside the matrix.  A prefetched value
-// waits kPf rows in a ring of kPfR > kPf slots.
-static_assert(kRing >= 2 * kBand && kPf < kPfR && kRing % kPfR == 0, "ring too short for the sweep windows");
+constexpr int kBlk1 = 24;  // rows per unrolled block of sweep 1
+constexpr int kBlk2 = 24;  // rows per unrolled block of sweeps 2 and 3 (they load)
+constexpr int kWin = 12;   // slots of the rolling windows of the recurrences
+constexpr int kPf = 23;    // rows of prefetch distance for the kept vector
+constexpr int kPfR = 24;   // slots of the prefetch ring
+// A row's window slot is its position in the block mod kWin (mod kPfR for
+// the prefetch ring), a constant of the unrolled body; the windows hold the
+// last 8 values (L and U solves) and the last 11 (eps for the G product).
+static_assert(kWin > 2 * kGB && kWin > kBand && kBlk1 % kWin == 0 && kBlk2 % kWin == 0,
+              "windows must divide the blocks");
+static_assert(kPf < kPfR && kBlk2 % kPfR == 0 && kBlk1 >= 2 * kBand && kBlk2 >= 2 * kBand,
+              "prefetch ring must divide the blocks");
 
 // LDS carve-up (floats) for up to 3*NMAX rows.  HB and NL are written only
 // after the assembly has read the solver's LDS mirrors, so they reuse the
@@ -89,6 +100,10 @@ struct BufRes {
     __device__ void st(float v, uint32_t voff, uint32_t soff) const {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
     }
+    // non-temporal store (output written once and not read back here)
+    __device__ void st_nt(float v, uint32_t voff, uint32_t soff) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 2);
+    }
 };
 
 // A wave-uniform row index copied into a VGPR.  LDS reads at "array + f(row)
@@ -114,10 +129,14 @@ __device__ __forceinline__ void sym_to_full(const float s[6], float m[3][3]) {
 // LDS reads of a step are issued together before any of its writes (the
 // entries a step updates are not read again within the step), so a step
 // costs one LDS round trip; steps depend on each other only through LDS,
-// whose reads and writes a wavefront performs in program order.  Rows past
-// N act as identity rows.  Returns false if a pivot was not positive (it is
-// then replaced by 1 so that the sweeps stay finite).
-__device__ __forceinline__ bool band_cholesky(float* C, float* Dg, int N) {
+// whose reads and writes a wavefront performs in program order.  Lanes with
+// nothing to write at a step write to their own slot of `sink` (64 floats of
+// LDS not in use during the factorization) instead of branching, and every
+// lane reads its target at an address inside the workgroup's LDS.  The
+// pivot's inverse square root is the hardware approximation (within 1 ulp).
+// Rows past N act as identity rows.  Returns false if a pivot was not
+// positive (it is then replaced by 1 so that the sweeps stay finite).
+__device__ __forceinline__ bool band_cholesky(float* C, float* Dg, int N, float* sink) {
     const int lane = (int)threadIdx.x & 63;
     // lanes 0..35 -> (a, b), 1 <= a <= b <= 8, column-major over b
     int ua = 0, ub = 0;
@@ -130,36 +149,58 @@ __device__ __forceinline__ bool band_cholesky(float* C, float* Dg, int N) {
     const bool upd = lane < 36;
     const bool scl = lane >= 1 && lane <= kBand;
     // update target of this lane, relative to step k: Dg[k + a] or C[k + a][b - a - 1]
+    // (lanes 36..63 point into C at rows up to 28 past k: inside the LDS
+    // that follows C, read and never written)
     float* const tgt0 = (ua == ub) ? Dg + ua : C + ua * 8 + (ub - ua) - 1;
     const int tstride = (ua == ub) ? 1 : 8;
     const int ca = upd ? ua - 1 : 0, cb = upd ? ub - 1 : 0, cm = scl ? lane - 1 : 0;
+    float* const sk = sink + lane;
     bool ok = true;
     for (int k = 0; k < N; ++k) {
         const bool live = upd && k + ub < N;
         float* const tgt = tgt0 + k * tstride;
         float d = Dg[k];
         const float xa = C[k * 8 + ca], xb = C[k * 8 + cb], xm = C[k * 8 + cm];
-        const float tv = live ? *tgt : 0.f;
+        const float tv = *tgt;
         __builtin_amdgcn_wave_barrier();
         ok = ok && (d > 0.f);
         d = d > 0.f ? d : 1.f;
-        const float is = 1.0f / sqrtf(d);
-        if (scl) C[k * 8 + lane - 1] = (k + lane < N) ? xm * is : 0.f;
-        if (lane == 0) Dg[k] = is;
-        if (live) *tgt = tv - (xa * is) * (xb * is);
+        const float is = __builtin_amdgcn_rsqf(d);
+        *(scl ? C + k * 8 + lane - 1 : sk) = (k + lane < N) ? xm * is : 0.f;
+        *(lane == 0 ? Dg + k : sk) = is;
+        *(live ? tgt : sk) = tv - (xa * is) * (xb * is);
         __builtin_amdgcn_wave_barrier();
     }
     return ok;
 }
 
+// Floats of scratch per workgroup: one vector of 3 NMAX rows per lane.
+template <int NT, int NMAX>
+constexpr size_t kept_slot_floats() { return (size_t)NT * 3 * NMAX; }
+
+// Scratch slots: XCDs x shader engines x CU ids x workgroup slots per CU.
+constexpr int kSlotXcc = 8, kSlotSe = 4, kSlotCu = 16;
+__host__ __device__ constexpr int kept_slots(int wg_per_cu) { return kSlotXcc * kSlotSe * kSlotCu * wg_per_cu; }
+
+// This workgroup's scratch slot from the hardware registers (wave-uniform),
+// or -1 if a field lies outside the table.  HW_ID: CU_ID bits 8-11, SE_ID
+// bits 13-15, TG_ID (workgroup slot on the CU) bits 16-19.
+__device__ __forceinline__ int hw_slot(int wg_per_cu) {
+    unsigned hw, xcc;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_HW_ID)" : "=s"(hw));
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+    const int cu = (hw >> 8) & 15, se = (hw >> 13) & 7, tg = (hw >> 16) & 15, x = xcc & 15;
+    if (x >= kSlotXcc || se >= kSlotSe || tg >= wg_per_cu) return -1;
+    return ((x * kSlotSe + se) * kSlotCu + cu) * wg_per_cu + tg;
+}
+
+// One item: the A_t (and B_t) of instance `id` at step t.
 template <int NT, int NMAX, int NOBS>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void linearize_direct_kernel(KArgs a) {
+__device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, const int t) {
     static_assert(NT % 64 == 0 && NT >= 3 * NMAX && NT >= 128, "one lane per column, two factor waves");
     using LL = LinLds<NMAX>;
     extern __shared__ float lds[];
-    const int id = a.ids[blockIdx.x];
     const InstDev& I = a.inst[id];
-    const int t = blockIdx.y;
     if (t >= I.T) return;
     Solver<kRope, NT, 1, NOBS> S;
     S.init(I, lds);
@@ -380,8 +421,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
         // wavefront 0 factors H_ff, wavefront 1 the reversed K_ff
         const int wv = threadIdx.x >> 6;
         bool ok = true;
-        if (wv == 0) ok = band_cholesky(LC, LI, N);
-        else if (wv == 1) ok = band_cholesky(UW, UD, N);
+        // UR is written only after both factorizations: its first 128
+        // floats are the two wavefronts' sinks
+        if (wv == 0) ok = band_cholesky(LC, LI, N, UR);
+        else if (wv == 1) ok = band_cholesky(UW, UD, N, UR + 64);
         if (!ok && (threadIdx.x & 63) == 0 && a.status) atomicMax(&a.status[id], kStNotPD);
     }
     __syncthreads();
@@ -406,16 +449,38 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
         const uint32_t rs = (uint32_t)ns * 4u;                  // bytes per row of A_t
         const uint32_t vJ = 4u * (uint32_t)j, vJN = 4u * (uint32_t)(N + j);
         const uint32_t vNJ = (uint32_t)N * rs + vJ, vK = (uint32_t)N * rs + vJN;
-        // vK: the kept vector, column j of the dv+/dv block
         const int pj = j / 3, cj = j - 3 * pj;
         const bool fj = jok && RF[jok ? j : 0] != 0.f;
         // first row that can be nonzero in w1 for any column of this
         // wavefront (wave-uniform: kept in a scalar register)
         const int i0 = __builtin_amdgcn_readfirstlane(max(0, (int)(threadIdx.x & ~63) - kBand));
+        // kept vector of this lane: row r at byte rS-base + vS + r krow;
+        // wbase + (r - i0) krow + wl addresses row r >= i0 for a window
+        const int wf = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        const int slot = a.kept ? hw_slot(a.kept_tg) : -1;
+        const float* kbase;
+        uint32_t kbytes, vS, krow, wl;
+        const float* wbase;
+        if (slot >= 0) {   // scratch [wavefront][row][lane], 256 bytes a row
+            kbase = a.kept + (size_t)slot * kept_slot_floats<NT, NMAX>();
+            kbytes = (uint32_t)(NT * LL::N3 * 4);
+            vS = (uint32_t)(wf * LL::N3) * 256u + 4u * (threadIdx.x & 63);
+            krow = 256u;
+            wl = 4u * (threadIdx.x & 63);
+            wbase = kbase + (wf * LL::N3 + i0) * 64;
+        } else {           // column j of the dv+/dv block of A_t
+            kbase = At;
+            kbytes = (uint32_t)ns * (uint32_t)ns * 4u;
+            vS = vK;
+            krow = rs;
+            wl = 4u * (uint32_t)j;
+            wbase = At + (int64_t)(N + i0) * ns + N;
+        }
+        const BufRes rS(kbase, kbytes);
 
-        // Each sweep runs in blocks of kRing rows whose body is unrolled, so
-        // the ring slot of a row (its position mod kRing) is a constant and
-        // the rolling windows stay in registers.  Blocks that cannot reach
+        // Each sweep runs in blocks of rows whose body is unrolled, so the
+        // window slot of a row is a constant and the rolling windows stay in
+        // registers.  Blocks that cannot reach
         // past either end of the matrix run a body without any condition
         // (one basic block, so its LDS reads can be issued ahead of the
         // arithmetic); the first and last blocks run the guarded body.  Sums
@@ -426,16 +491,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
         // sweep 1: w1 = L^{-1} r1 for rows i0..N-1 (rows above i0 are zero
         // for every column of this wavefront and are not stored)
         if (jok) {
-            float w[kRing];
+            float w[kWin];
 #pragma unroll
-            for (int u = 0; u < kRing; ++u) w[u] = 0.f;
-            for (int tb = 0; i0 + tb < N; tb += kRing) {
+            for (int u = 0; u < kWin; ++u) w[u] = 0.f;
+            for (int tb = 0; i0 + tb < N; tb += kBlk1) {
                 const int r0 = i0 + tb;                         // row of u = 0
                 const float* LCb = lds + vrow((int)(LC - lds) + (r0 - kBand) * 8);   // L(i, i-m) at LCb[(u+kBand-m)*8 + m-1]
                 const float* LIb = lds + vrow((int)(LI - lds) + r0);
                 const float* RFb = lds + vrow((int)(RF - lds) + r0);
                 const int db = r0 - j;
-                const uint32_t so = (uint32_t)r0 * rs;
                 auto row = [&](const int u, const bool guard) {
                     const int i = r0 + u;
                     if (guard && i >= N) return;
@@ -448,17 +512,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
                     float acc = (dd == ddc) ? -rfi * h : 0.f;
 #pragma unroll
                     for (int m = kBand; m >= 1; --m)
-                        if (!guard || i - m >= i0) acc -= LCb[(u + kBand - m) * 8 + m - 1] * w[(u - m + kRing) % kRing];
+                        if (!guard || i - m >= i0) acc -= LCb[(u + kBand - m) * 8 + m - 1] * w[(u - m + kWin) % kWin];
                     const float wi = acc * LIb[u];
-                    w[u] = wi;
-                    rA.st(wi, vK, so + (uint32_t)u * rs);
+                    w[u % kWin] = wi;
+                    rS.st(wi, vS, (uint32_t)(r0 + u) * krow);
                 };
-                if (tb > 0 && r0 + kRing <= N) {
+                if (tb > 0 && r0 + kBlk1 <= N) {
 #pragma unroll
-                    for (int u = 0; u < kRing; ++u) row(u, false);
+                    for (int u = 0; u < kBlk1; ++u) row(u, false);
                 } else {
 #pragma unroll
-                    for (int u = 0; u < kRing; ++u) row(u, true);
+                    for (int u = 0; u < kBlk1; ++u) row(u, true);
                 }
             }
         }
@@ -467,18 +531,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
             // loads of w1 through a window that starts at row i0: rows above
             // it fall outside the window (the lane offset wraps past its
             // size) and read as zero without touching memory
-            const BufRes rK(At + (int64_t)(N + i0) * ns + N, (uint32_t)(N - i0) * rs);
-            const uint32_t vW = 4u * (uint32_t)j;
-            float e[kRing], w2[kRing], pf[kPfR];
+            const BufRes rK(wbase, (uint32_t)(N - i0) * krow);
+            const uint32_t vW = wl;
+            float e[kWin], w2[kWin], pf[kPfR];
 #pragma unroll
-            for (int u = 0; u < kRing; ++u) { e[u] = 0.f; w2[u] = 0.f; }
+            for (int u = 0; u < kWin; ++u) { e[u] = 0.f; w2[u] = 0.f; }
 #pragma unroll
             for (int u = 0; u < kPfR; ++u) pf[u] = 0.f;
 #pragma unroll
-            for (int u = 0; u < kPf; ++u) pf[u] = rK.ld(vW + (uint32_t)(N - 1 - u - i0) * rs, 0);
-            for (int sb = 0; sb < N + kGB; sb += kRing) {
-                // row of position sb+u is i = ib + v, v = kRing-1-u
-                const int ib = N - kRing - sb;
+            for (int u = 0; u < kPf; ++u) pf[u] = rK.ld(vW + (uint32_t)(N - 1 - u - i0) * krow, 0);
+            for (int sb = 0; sb < N + kGB; sb += kBlk2) {
+                // row of position sb+u is i = ib + v, v = kBlk2-1-u
+                const int ib = N - kBlk2 - sb;
                 const int mb = ib + kGB;                        // mrow = mb + v
                 const float* LCb = lds + vrow((int)(LC - lds) + ib * 8);
                 const float* LIb = lds + vrow((int)(LI - lds) + ib);
@@ -488,15 +552,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
                 const float* NLb = NL + mb * 3 + cj;
                 const float* UDb = lds + vrow((int)(UD - lds) + sb - kGB);   // UD[N-1-mrow] = UDb[u]
                 const int qb = j - mb;                          // dq = j - mrow = qb - v
-                const uint32_t vpf = vW + (uint32_t)(ib - kPf - i0) * rs;   // row i-kPf = ib-kPf+v
-                const uint32_t som = (uint32_t)mb * rs;
+                const uint32_t vpf = vW + (uint32_t)(ib - kPf - i0) * krow;   // row i-kPf = ib-kPf+v
                 auto row = [&](const int u, const bool guard) {
-                    const int v = kRing - 1 - u;
+                    const int v = kBlk2 - 1 - u;
                     const int sp = sb + u;
                     const int i = ib + v;
                     if (guard && sp >= N + kGB) return;
                     // kept w1 kPf rows ahead
-                    pf[(u + kPf) % kPfR] = rK.ld(vpf + (uint32_t)v * rs, 0);
+                    pf[(u + kPf) % kPfR] = rK.ld(vpf + (uint32_t)v * krow, 0);
                     float ei = 0.f;
                     if (!guard || i >= 0) {
                         const float4 l0 = *reinterpret_cast<const float4*>(LCb + v * 8);
@@ -504,11 +567,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
                         const float lc[8] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
                         float acc = pf[u % kPfR];
 #pragma unroll
-                        for (int m = kBand; m >= 1; --m) acc -= lc[m - 1] * e[(u - m + kRing) % kRing];
+                        for (int m = kBand; m >= 1; --m) acc -= lc[m - 1] * e[(u - m + kWin) % kWin];
                         ei = acc * LIb[v];
                     }
-                    e[u] = ei;
-                    if (guard && i + kGB >= N) { w2[u] = 0.f; return; }
+                    e[u % kWin] = ei;
+                    if (guard && i + kGB >= N) { w2[u % kWin] = 0.f; return; }
                     // column-local part: G(m, j) - H_el(m, j) - [same particle] NLN(m, j)
                     // (a same-particle column of a free row is free)
                     const int dq = qb - v;
@@ -525,25 +588,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
                     const float4 g2 = *reinterpret_cast<const float4*>(GBb + v * 12 + 8);
                     const float gr[12] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w, g2.x, g2.y, g2.z, g2.w};
 #pragma unroll
-                    for (int qq = 2 * kGB; qq >= 0; --qq) r += gr[qq] * e[(u - qq + kRing) % kRing];
+                    for (int qq = 2 * kGB; qq >= 0; --qq) r += gr[qq] * e[(u - qq + kWin) % kWin];
                     r *= RFb[v];
                     const float4 q0 = *reinterpret_cast<const float4*>(URb + v * 8);
                     const float4 q1 = *reinterpret_cast<const float4*>(URb + v * 8 + 4);
                     const float ur[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
                     float pre = 0.f;
 #pragma unroll
-                    for (int q = kBand; q >= 2; --q) pre += ur[q - 1] * w2[(u - q + kRing) % kRing];
-                    const float acc = (r - pre) - ur[0] * w2[(u - 1 + kRing) % kRing];
+                    for (int q = kBand; q >= 2; --q) pre += ur[q - 1] * w2[(u - q + kWin) % kWin];
+                    const float acc = (r - pre) - ur[0] * w2[(u - 1 + kWin) % kWin];
                     const float wv = acc * UDb[u];
-                    w2[u] = wv;
-                    rA.st(wv, vK, som + (uint32_t)v * rs);
+                    w2[u % kWin] = wv;
+                    rS.st(wv, vS, (uint32_t)(mb + v) * krow);
                 };
-                if (sb >= kGB && sb + kRing <= N) {
+                if (sb >= kGB && sb + kBlk2 <= N) {
 #pragma unroll
-                    for (int u = 0; u < kRing; ++u) row(u, false);
+                    for (int u = 0; u < kBlk2; ++u) row(u, false);
                 } else {
 #pragma unroll
-                    for (int u = 0; u < kRing; ++u) row(u, true);
+                    for (int u = 0; u < kBlk2; ++u) row(u, true);
                 }
             }
         }
@@ -557,48 +620,47 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
             for (int g = 0; g < I.n_grip; ++g)
                 if (I.grip_node[g] == pj) gj = g;
             float* const bsl = gj >= 0 ? BS + (3 * gj + cj) * LL::N3 : BD + j;
-            float E[kRing], pf[kPfR];
+            float E[kWin], pf[kPfR];
 #pragma unroll
-            for (int u = 0; u < kRing; ++u) E[u] = 0.f;
+            for (int u = 0; u < kWin; ++u) E[u] = 0.f;
 #pragma unroll
             for (int u = 0; u < kPfR; ++u) pf[u] = 0.f;
 #pragma unroll
-            for (int u = 0; u < kPf; ++u) pf[u] = rA.ld(vK, (uint32_t)min(u, N - 1) * rs);
+            for (int u = 0; u < kPf; ++u) pf[u] = rS.ld(vS, (uint32_t)min(u, N - 1) * krow);
             const float c1 = dt * (1.f - gam), omg = 1.f - gam;
             const float cv = fj ? c1 : 0.f, vv = fj ? omg : 0.f;
-            for (int tb = 0; tb < N; tb += kRing) {
-                // U(i-q, i) at UWb[(kRing-1-u)*8 + q-1], 1/U(i,i) at UDb[kRing-1-u]
-                const float* UWb = lds + vrow((int)(UW - lds) + (N - kRing - tb) * 8);
-                const float* UDb = lds + vrow((int)(UD - lds) + N - kRing - tb);
+            for (int tb = 0; tb < N; tb += kBlk2) {
+                // U(i-q, i) at UWb[(kBlk2-1-u)*8 + q-1], 1/U(i,i) at UDb[kBlk2-1-u]
+                const float* UWb = lds + vrow((int)(UW - lds) + (N - kBlk2 - tb) * 8);
+                const float* UDb = lds + vrow((int)(UD - lds) + N - kBlk2 - tb);
                 float* const bsb = bsl + tb;
                 const uint32_t so = (uint32_t)tb * rs;
                 auto row = [&](const int u, const bool guard) {
                     const int i = tb + u;
                     if (guard && i >= N) return;
-                    pf[(u + kPf) % kPfR] = rA.ld(vK, guard ? (uint32_t)min(i + kPf, N - 1) * rs
-                                                            : so + (uint32_t)(u + kPf) * rs);
-                    const float4 c0 = *reinterpret_cast<const float4*>(UWb + (kRing - 1 - u) * 8);
-                    const float4 c1v = *reinterpret_cast<const float4*>(UWb + (kRing - 1 - u) * 8 + 4);
+                    pf[(u + kPf) % kPfR] = rS.ld(vS, (uint32_t)(guard ? min(i + kPf, N - 1) : i + kPf) * krow);
+                    const float4 c0 = *reinterpret_cast<const float4*>(UWb + (kBlk2 - 1 - u) * 8);
+                    const float4 c1v = *reinterpret_cast<const float4*>(UWb + (kBlk2 - 1 - u) * 8 + 4);
                     const float uc[8] = {c0.x, c0.y, c0.z, c0.w, c1v.x, c1v.y, c1v.z, c1v.w};
                     float acc = pf[u % kPfR];
 #pragma unroll
-                    for (int q = kBand; q >= 1; --q) acc -= uc[q - 1] * E[(u - q + kRing) % kRing];
-                    const float Ei = acc * UDb[kRing - 1 - u];
-                    E[u] = Ei;
+                    for (int q = kBand; q >= 1; --q) acc -= uc[q - 1] * E[(u - q + kWin) % kWin];
+                    const float Ei = acc * UDb[kBlk2 - 1 - u];
+                    E[u % kWin] = Ei;
                     const float dx = (i == j ? 1.f : 0.f) + Ei;
                     const uint32_t sr = so + (uint32_t)u * rs;
-                    rA.st(dx, vJ, sr);
-                    rA.st(Ei * idt, vNJ, sr);
-                    rA.st(cv * dx, vJN, sr);
-                    rA.st(vv * dx, vK, sr);
+                    rA.st_nt(dx, vJ, sr);
+                    rA.st_nt(Ei * idt, vNJ, sr);
+                    rA.st_nt(cv * dx, vJN, sr);
+                    rA.st_nt(vv * dx, vK, sr);
                     bsb[u] = dx;
                 };
-                if (tb + kRing + kPf <= N) {
+                if (tb + kBlk2 + kPf <= N) {
 #pragma unroll
-                    for (int u = 0; u < kRing; ++u) row(u, false);
+                    for (int u = 0; u < kBlk2; ++u) row(u, false);
                 } else {
 #pragma unroll
-                    for (int u = 0; u < kRing; ++u) row(u, true);
+                    for (int u = 0; u < kBlk2; ++u) row(u, true);
                 }
             }
         }
@@ -609,8 +671,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
             for (int idx = threadIdx.x; idx < N * nu; idx += NT) {
                 const int i = idx / nu, s = idx - i * nu;
                 const float v = BS[s * LL::N3 + i];
-                Bt[(int64_t)i * nu + s] = dt * v;
-                Bt[(int64_t)(N + i) * nu + s] = v;
+                __builtin_nontemporal_store(dt * v, Bt + (int64_t)i * nu + s);
+                __builtin_nontemporal_store(v, Bt + (int64_t)(N + i) * nu + s);
             }
         }
     }
@@ -619,9 +681,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void li
         for (int i = 0; i < 4; ++i) atomicAdd(&a.counters[4 * id + i], S.cnt[i]);
 }
 
+// Grid (blocks of a.ids, steps): one workgroup per (instance, step).
+template <int NT, int NMAX, int NOBS>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void linearize_direct_kernel(KArgs a) {
+    lin_direct_item<NT, NMAX, NOBS>(a, a.ids[blockIdx.x], (int)blockIdx.y);
+}
+
 template <int NT, int NMAX, int NOBS>
 struct LinDirect {
     static constexpr size_t kLds = sizeof(float) * (lds_floats<NT, 1>() + LinLds<NMAX>::TOTAL);
+    static constexpr size_t kSlot = kept_slot_floats<NT, NMAX>();
+    static int resident_per_cu() {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, linearize_direct_kernel<NT, NMAX, NOBS>, NT, kLds) !=
+            hipSuccess)
+            nb = 0;
+        return nb;
+    }
     static hipError_t launch(const KArgs& a, int nblk, int tmax, hipStream_t s) {
         hipLaunchKernelGGL((linearize_direct_kernel<NT, NMAX, NOBS>), dim3(nblk, tmax), dim3(NT), kLds, s, a);
         return hipGetLastError();

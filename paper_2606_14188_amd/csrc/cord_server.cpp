@@ -246,6 +246,8 @@ void release_blocks(cord_server* s, Req* q) {
 
 // Carve every device buffer of the request from the arena; false (and
 // nothing held) if the free space is too fragmented.
+float* no_kept(void*, size_t) { return nullptr; }
+
 bool carve_all(cord_server* s, Req* q) {
     const int C = q->C, T = q->T, ns = q->ns, nu = q->nu;
     const bool ab = q->r.want_AB != 0;
@@ -373,8 +375,9 @@ bool enqueue(cord_server* s, Req* q) {
         l.status = nullptr;
         l.aux = q->d_aux; l.aux_mode = 2;
         const int topo = q->r.inst.kind == CORD_ROPE ? kRope : kCloth;
+        // one instance: the direct kernel keeps its vectors inside A (no scratch)
         SRV_HIP(launch_linearize(q->cfg, topo, bucket_of(topo, q->n), q->r.inst.grip_mode == CORD_GRIP_PENALTY, l, 1,
-                                 T, st));
+                                 T, st, KeptSource{&no_kept, nullptr}));
     }
     // result download into the slot's staging
     char* h = sg.down;
