@@ -78,7 +78,9 @@ hipError_t launch_linearize(int cfg_index, int topo, int nmax, bool penalty, con
     if (wg > 0) {
         KArgs ad = a;
         ad.jvp_k = 0; ad.jvp_ds = nullptr; ad.jvp_du = nullptr; ad.jvp_out = nullptr;
-        ad.kept = ks.get(ks.ctx, kf);   // null: vectors kept inside A
+        // null: vectors kept inside A (also forced by CORD_LINEARIZE_NO_SCRATCH=1)
+        const char* ns = std::getenv("CORD_LINEARIZE_NO_SCRATCH");
+        ad.kept = (ns && ns[0] == '1') ? nullptr : ks.get(ks.ctx, kf);
         ad.kept_tg = wg;
         hipError_t e = linearize_rope_direct(nmax, ad, nblk, tmax, st);
         if (e != hipSuccess || !a.jvp_out) return e;

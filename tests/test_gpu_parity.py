@@ -312,6 +312,37 @@ def test_linearize_b_only_and_with_jvp():
             assert eb <= JAC_TOL
 
 
+def test_linearize_scratch_and_in_place_agree(monkeypatch):
+    """The direct rope linearization keeps each column's intermediate vector
+    in the scratch table indexed by the hardware workgroup slot, or (without
+    the table) inside A_t.  Both run the same arithmetic: A_t and B_t agree
+    bitwise, for ropes of all three direct size classes in one batch, and the
+    default path matches the oracle."""
+    import torch
+    insts = (W.small_rope_batch(3, 30, 6, seed=481) + W.small_rope_batch(3, 64, 5, seed=482)
+             + W.small_rope_batch(2, 100, 4, seed=483))
+    sim, s0, u, traj, st = _run(insts)
+    assert (st == 0).all()
+    A1, B1, _ = sim.linearize(traj, u)
+    torch.cuda.synchronize()
+    monkeypatch.setenv("CORD_LINEARIZE_NO_SCRATCH", "1")
+    A2, B2, _ = sim.linearize(traj, u)
+    torch.cuda.synchronize()
+    assert torch.equal(A1, A2) and torch.equal(B1, B2)
+    Ap, Bp, tp = sim.split(A1, "A"), sim.split(B1, "B"), sim.split(traj, "traj")
+    for j in (0, 3, 7):
+        inst = insts[j]
+        tr = tp[j].reshape(inst.T + 1, inst.n_s).astype(np.float64)
+        t = inst.T - 1
+        Ar, Br = StepDerivative(inst, tr[t], inst.u[t], inst.kappa_bwd).dense()
+        Aj = Ap[j].reshape(inst.T, inst.n_s, inst.n_s)[t]
+        Bj = Bp[j].reshape(inst.T, inst.n_s, inst.n_u)[t]
+        ea = np.linalg.norm(Aj - Ar) / np.linalg.norm(Ar)
+        eb = np.linalg.norm(Bj - Br) / np.linalg.norm(Br)
+        print(f"rope {inst.n} t={t}: A err {ea:.2e} B err {eb:.2e}", flush=True)
+        assert ea <= JAC_TOL and eb <= JAC_TOL
+
+
 def test_c2_linearize_full_size_sampled():
     """Dense A_t/B_t for the full 1024 x 64-node x 100-step rope batch in one
     launch (60 GB of A_t), sampled (instance, step) blocks against the oracle."""
