@@ -299,6 +299,13 @@ typedef struct {
  *   A   [T][n_s][n_s] row-major per instance, or NULL
  *   Bm  [T][n_s][n_u] row-major per instance, or NULL
  *   jvp JVP mode (may be NULL); may be combined with A/Bm.
+ * For ropes of up to 128 particles with a Dirichlet grasp, A/Bm come from
+ * the banded direct kernel; the simulator then keeps a device scratch table
+ * for it (allocated on the first such call: 302 MB for the 64-particle
+ * class on MI355X, of which the resident workgroups touch 151 MB; if that
+ * allocation fails the kernel works without it, at lower speed, with
+ * bitwise the same results).  Linearize calls on one
+ * simulator share that table: calls on different streams must not overlap.
  * Errors: CORD_EINVAL if A, Bm and jvp are all NULL.
  */
 int cord_linearize(cord_sim* sim, const float* traj, const float* u, float* A, float* Bm,
