@@ -248,6 +248,7 @@ struct Solver {
     float x[PPT][3], v[PPT][3], d[PPT][3], dl[PPT][3], ug[PPT][3];
     float se[PPT][NS][3], sa[PPT][NS], sb[PPT][NS];
     float Bd[PPT][6], Mi[PPT][6];
+    float bw[PPT][3];       // rope: bending weights of the centres p-1, p, p+1 (zero if not a centre)
     float cn[PPT][NOBS][3], cphi[PPT][NOBS], clam[PPT][NOBS], cgap[PPT][NOBS];
 
     int status;
@@ -294,6 +295,13 @@ struct Solver {
                 for (int f = 0; f < 16; ++f) pg(k)[f] = 0.f;
             px[k] = (TOPO == kCloth) ? p % nx : p;
             py[k] = (TOPO == kCloth) ? p / nx : 0;
+            // d/dx_p of the bending energy: the centres cc = p-1, p, p+1 that
+            // lie in [1, n-2] carry the stencil (1, -2, 1), weighted 1, -2, 1
+#pragma unroll
+            for (int j = -1; j <= 1; ++j) {
+                const int cc = p + j;
+                bw[k][j + 1] = (TOPO == kRope && cc >= 1 && cc <= n - 2) ? ((j == 0) ? -2.f : 1.f) * kb : 0.f;
+            }
 #pragma unroll
             for (int c = 0; c < 3; ++c) { x[k][c] = 0.f; v[k][c] = 0.f; d[k][c] = 0.f; dl[k][c] = 0.f; ug[k][c] = 0.f; }
         }
@@ -496,36 +504,60 @@ struct Solver {
             if (!active(k)) continue;
             if (!isfree(k) && !grip_rows) continue;
             float wp[3];
-            get(V, p, wp);
-            if (isfree(k) && with_mass) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) q[k][c] = mdt2 * wp[c];
-            }
-            if (pen[k] >= 0) {
-                const float Dv = pg(k)[6];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) q[k][c] += Dv * wp[c];
-            }
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const int nq = nbr(k, p, s);
-                if (nq < 0) continue;
-                float wq[3];
-                get(V, nq, wq);
-                float dv[3] = {wp[0] - wq[0], wp[1] - wq[1], wp[2] - wq[2]};
-                const float t = sa[k][s] * dot3(se[k][s], dv);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) q[k][c] += t * se[k][s][c] + sb[k][s] * dv[c];
-            }
             if constexpr (TOPO == kRope) {
+                // V at p-2..p+2 (indices clamped into the rope: the springs
+                // and bending weights of missing neighbours are zero), then
+                // the springs to p+1 and p-1 and the curvature at the three
+                // centres, without branches (same arithmetic as the
+                // neighbour-by-neighbour form)
+                float w5[5][3];
 #pragma unroll
-                for (int j = -1; j <= 1; ++j) {
-                    const int cc = p + j;
-                    if (cc < 1 || cc > n - 2) continue;
-                    const float w = ((j == 0) ? -2.f : 1.f) * kb;
+                for (int e = 0; e < 5; ++e) get(V, min(max(p + e - 2, 0), n - 1), w5[e]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) wp[c] = w5[2][c];
+                if (isfree(k) && with_mass) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) q[k][c] = mdt2 * wp[c];
+                }
+                if (pen[k] >= 0) {
+                    const float Dv = pg(k)[6];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) q[k][c] += Dv * wp[c];
+                }
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const float* wq = w5[2 + TP::dx(s)];
+                    float dv[3] = {wp[0] - wq[0], wp[1] - wq[1], wp[2] - wq[2]};
+                    const float t = sa[k][s] * dot3(se[k][s], dv);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) q[k][c] += t * se[k][s][c] + sb[k][s] * dv[c];
+                }
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
-                        q[k][c] += w * (V[c * NM + cc - 1] - 2.f * V[c * NM + cc] + V[c * NM + cc + 1]);
+                        q[k][c] += bw[k][j] * (w5[j][c] - 2.f * w5[j + 1][c] + w5[j + 2][c]);
+            } else {
+                get(V, p, wp);
+                if (isfree(k) && with_mass) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) q[k][c] = mdt2 * wp[c];
+                }
+                if (pen[k] >= 0) {
+                    const float Dv = pg(k)[6];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) q[k][c] += Dv * wp[c];
+                }
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const int nq = nbr(k, p, s);
+                    if (nq < 0) continue;
+                    float wq[3];
+                    get(V, nq, wq);
+                    float dv[3] = {wp[0] - wq[0], wp[1] - wq[1], wp[2] - wq[2]};
+                    const float t = sa[k][s] * dot3(se[k][s], dv);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) q[k][c] += t * se[k][s][c] + sb[k][s] * dv[c];
                 }
             }
             if constexpr (CONTACT) {
