@@ -454,6 +454,9 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
         // first row that can be nonzero in w1 for any column of this
         // wavefront (wave-uniform: kept in a scalar register)
         const int i0 = __builtin_amdgcn_readfirstlane(max(0, (int)(threadIdx.x & ~63) - kBand));
+        // rows that can carry a column-local right-hand-side term for some
+        // column of this wavefront: |row - j| <= 8 for j in j0..j0+63
+        const int jl0 = i0, jl1 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63) + 63 + kBand);
         // kept vector of this lane: row r at byte rS-base + vS + r krow;
         // wbase + (r - i0) krow + wl addresses row r >= i0 for a window
         const int wf = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -500,16 +503,19 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
                 const float* LIb = lds + vrow((int)(LI - lds) + r0);
                 const float* RFb = lds + vrow((int)(RF - lds) + r0);
                 const int db = r0 - j;
-                auto row = [&](const int u, const bool guard) {
+                auto row = [&](const int u, const bool guard, const bool loc) {
                     const int i = r0 + u;
                     if (guard && i >= N) return;
-                    // -(H_el z)_f: H_el(max(i,j), min(i,j)) inside the band
-                    const int dd = db + u;
-                    const int ddc = min(max(dd, -kBand), kBand);
-                    const int hidx = 9 * j - ddc + (dd >= 0 ? 9 * dd + 2 * ddc : 0);
-                    const float h = HB[hidx];
-                    const float rfi = RFb[u];
-                    float acc = (dd == ddc) ? -rfi * h : 0.f;
+                    float acc = 0.f;
+                    if (loc) {
+                        // -(H_el z)_f: H_el(max(i,j), min(i,j)) inside the band
+                        const int dd = db + u;
+                        const int ddc = min(max(dd, -kBand), kBand);
+                        const int hidx = 9 * j - ddc + (dd >= 0 ? 9 * dd + 2 * ddc : 0);
+                        const float h = HB[hidx];
+                        const float rfi = RFb[u];
+                        acc = (dd == ddc) ? -rfi * h : 0.f;
+                    }
 #pragma unroll
                     for (int m = kBand; m >= 1; --m)
                         if (!guard || i - m >= i0) acc -= LCb[(u + kBand - m) * 8 + m - 1] * w[(u - m + kWin) % kWin];
@@ -518,11 +524,16 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
                     rS.st(wi, vS, (uint32_t)(r0 + u) * krow);
                 };
                 if (tb > 0 && r0 + kBlk1 <= N) {
+                    if (r0 <= jl1) {
 #pragma unroll
-                    for (int u = 0; u < kBlk1; ++u) row(u, false);
+                        for (int u = 0; u < kBlk1; ++u) row(u, false, true);
+                    } else {   // no column of this wavefront reaches these rows
+#pragma unroll
+                        for (int u = 0; u < kBlk1; ++u) row(u, false, false);
+                    }
                 } else {
 #pragma unroll
-                    for (int u = 0; u < kBlk1; ++u) row(u, true);
+                    for (int u = 0; u < kBlk1; ++u) row(u, true, true);
                 }
             }
         }
@@ -553,7 +564,7 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
                 const float* UDb = lds + vrow((int)(UD - lds) + sb - kGB);   // UD[N-1-mrow] = UDb[u]
                 const int qb = j - mb;                          // dq = j - mrow = qb - v
                 const uint32_t vpf = vW + (uint32_t)(ib - kPf - i0) * krow;   // row i-kPf = ib-kPf+v
-                auto row = [&](const int u, const bool guard) {
+                auto row = [&](const int u, const bool guard, const bool loc) {
                     const int v = kBlk2 - 1 - u;
                     const int sp = sb + u;
                     const int i = ib + v;
@@ -574,14 +585,17 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
                     if (guard && i + kGB >= N) { w2[u % kWin] = 0.f; return; }
                     // column-local part: G(m, j) - H_el(m, j) - [same particle] NLN(m, j)
                     // (a same-particle column of a free row is free)
-                    const int dq = qb - v;
-                    const int dqc = min(max(dq, -kBand), kBand), dgc = min(max(dq, -kGB), kGB);
-                    const int hidx = 9 * j + dqc - (dq <= 0 ? 9 * dq + 2 * dqc : 0);
-                    const float hv = HB[hidx];
-                    const float gv = GBb[v * 12 + kGB + dgc];
-                    const float nl = NLb[v * 3];
-                    const bool same = (uint32_t)(cj - dq) <= 2u;
-                    float r = ((dq == dgc) ? gv : 0.f) - (same ? nl : 0.f) - ((dq == dqc) ? hv : 0.f);
+                    float r = 0.f;
+                    if (loc) {
+                        const int dq = qb - v;
+                        const int dqc = min(max(dq, -kBand), kBand), dgc = min(max(dq, -kGB), kGB);
+                        const int hidx = 9 * j + dqc - (dq <= 0 ? 9 * dq + 2 * dqc : 0);
+                        const float hv = HB[hidx];
+                        const float gv = GBb[v * 12 + kGB + dgc];
+                        const float nl = NLb[v * 3];
+                        const bool same = (uint32_t)(cj - dq) <= 2u;
+                        r = ((dq == dgc) ? gv : 0.f) - (same ? nl : 0.f) - ((dq == dqc) ? hv : 0.f);
+                    }
                     // G(m, m-5..m+5) eps; e[(u - qq)] holds eps_{mrow - 5 + qq}
                     const float4 g0 = *reinterpret_cast<const float4*>(GBb + v * 12);
                     const float4 g1 = *reinterpret_cast<const float4*>(GBb + v * 12 + 4);
@@ -589,7 +603,7 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
                     const float gr[12] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w, g2.x, g2.y, g2.z, g2.w};
 #pragma unroll
                     for (int qq = 2 * kGB; qq >= 0; --qq) r += gr[qq] * e[(u - qq + kWin) % kWin];
-                    r *= RFb[v];
+                    if (loc) r *= RFb[v];   // (G rows of gripped particles are zero)
                     const float4 q0 = *reinterpret_cast<const float4*>(URb + v * 8);
                     const float4 q1 = *reinterpret_cast<const float4*>(URb + v * 8 + 4);
                     const float ur[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
@@ -602,11 +616,16 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
                     rS.st(wv, vS, (uint32_t)(mb + v) * krow);
                 };
                 if (sb >= kGB && sb + kBlk2 <= N) {
+                    if (mb + kBlk2 - 1 >= jl0 && mb <= jl1) {
 #pragma unroll
-                    for (int u = 0; u < kBlk2; ++u) row(u, false);
+                        for (int u = 0; u < kBlk2; ++u) row(u, false, true);
+                    } else {   // no column of this wavefront reaches these rows
+#pragma unroll
+                        for (int u = 0; u < kBlk2; ++u) row(u, false, false);
+                    }
                 } else {
 #pragma unroll
-                    for (int u = 0; u < kBlk2; ++u) row(u, true);
+                    for (int u = 0; u < kBlk2; ++u) row(u, true, true);
                 }
             }
         }
