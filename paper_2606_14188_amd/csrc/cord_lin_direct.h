@@ -5,10 +5,11 @@
 // (diff-sim)) couples a particle only with its neighbours up to distance 2
 // (stretch springs at distance 1, the bending stencil at distance 2).  In the
 // 3n scalar unknowns each is a band matrix of half-bandwidth 8, so one
-// workgroup per (instance, step) recomputes the step, assembles the bands
-// in LDS, factors H_ff = L L^T and K_ff = U U^T (U upper triangular: the
-// Cholesky factor of the index-reversed matrix) with one wavefront each,
-// and then every lane solves for one column j of the step map on its own.
+// workgroup per (instance, step) restores (or solves again) the step,
+// assembles the bands in LDS, factors H_ff = L L^T and K_ff = U U^T (U upper
+// triangular: the Cholesky factor of the index-reversed matrix) with one
+// wavefront each, and then every lane solves for one column j of the step
+// map on its own.
 //
 // Column j is the response E = dx+ - z to the unit predictor tangent z = e_j
 // (z is dxhat on free particles and the gripper displacement db on gripped
@@ -436,9 +437,10 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
 
     // ---------------------------------------------------------- column sweeps
     // Global accesses of the sweeps are raw buffer instructions over this
-    // step's A_t: a loop-invariant lane offset (VGPR) plus a wave-uniform row
-    // offset in bytes (SGPR).  LDS reads of a block of rows go through one
-    // base address per array and constant offsets.
+    // step's A_t and the kept vector's storage: a loop-invariant lane offset
+    // (VGPR) plus a wave-uniform row offset in bytes (SGPR).  LDS reads of a
+    // block of rows go through one base address per array and constant
+    // offsets.
     const int j = threadIdx.x;
     const bool jok = j < N;
     if (a.A) {
