@@ -446,6 +446,17 @@ struct Solver {
                     Bd[k][0] += G[6]; Bd[k][3] += G[6]; Bd[k][5] += G[6];
                 }
             }
+            // rope: X and D at p-2..p+2 read once (clamped indices; only the
+            // neighbours that exist are used below)
+            float x5[5][3], d5[5][3];
+            if constexpr (TOPO == kRope) {
+#pragma unroll
+                for (int e = 0; e < 5; ++e) {
+                    const int qe = min(max(p + e - 2, 0), n - 1);
+                    get(X, qe, x5[e]);
+                    get(D, qe, d5[e]);
+                }
+            }
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 const int q = nbr(k, p, s);
@@ -454,7 +465,11 @@ struct Solver {
                 const float kk = kS[ty], l0 = rS[ty];
                 float e[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) e[c] = (X[c * NM + q] - x[k][c]) + (D[c * NM + q] - d[k][c]);
+                for (int c = 0; c < 3; ++c) {
+                    const float xq = (TOPO == kRope) ? x5[2 + TP::dx(s)][c] : X[c * NM + q];
+                    const float dq = (TOPO == kRope) ? d5[2 + TP::dx(s)][c] : D[c * NM + q];
+                    e[c] = (xq - x[k][c]) + (dq - d[k][c]);
+                }
                 const float L = sqrtf(dot3(e, e));
                 const float il = 1.0f / L;
                 float eh[3] = {e[0] * il, e[1] * il, e[2] * il};
@@ -480,8 +495,8 @@ struct Solver {
                     wdiag += w * w;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const float kap = (X[c * NM + cc - 1] - 2.f * X[c * NM + cc] + X[c * NM + cc + 1]) +
-                                          (D[c * NM + cc - 1] - 2.f * D[c * NM + cc] + D[c * NM + cc + 1]);
+                        const float kap = (x5[j + 1][c] - 2.f * x5[j + 2][c] + x5[j + 3][c]) +
+                                          (d5[j + 1][c] - 2.f * d5[j + 2][c] + d5[j + 3][c]);
                         if (isfree(k)) F[k][c] += w * kb * kap;
                     }
                 }
