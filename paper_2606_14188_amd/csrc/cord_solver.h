@@ -309,7 +309,17 @@ struct Solver {
         cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0;
     }
 
-    __device__ __forceinline__ void sync() { __syncthreads(); }
+    // Orders the LDS mirrors between lanes.  A single wavefront performs its
+    // LDS reads and writes in issue order, so it needs only a compiler-level
+    // fence (no s_barrier, no wait for outstanding LDS operations).
+    __device__ __forceinline__ void sync() {
+        if constexpr (NT == 64) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            __syncthreads();
+        }
+    }
 
     // -------------------------------------------------- block reductions
     __device__ __forceinline__ float bsum(float v) {
