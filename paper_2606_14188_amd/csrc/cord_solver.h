@@ -680,6 +680,18 @@ struct Solver {
             if (!active(k)) continue;
             float sp[3];
             get(DL, p, sp);
+            // rope: X, D and DL at p-1..p+1 read once (clamped indices; only
+            // the neighbours that exist are used below)
+            float x3[3][3], d3[3][3], l3[3][3];
+            if constexpr (TOPO == kRope) {
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const int qe = min(max(p + e - 1, 0), n - 1);
+                    get(X, qe, x3[e]);
+                    get(D, qe, d3[e]);
+                    get(DL, qe, l3[e]);
+                }
+            }
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 const int q = nbr(k, p, s);
@@ -688,8 +700,12 @@ struct Solver {
                 float e0[3], de[3], e1[3], sm[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    e0[c] = (X[c * NM + q] - x[k][c]) + (D[c * NM + q] - d[k][c]);
-                    de[c] = DL[c * NM + q] - sp[c];
+                    const int eq = 1 + TP::dx(s);
+                    const float xq = (TOPO == kRope) ? x3[eq][c] : X[c * NM + q];
+                    const float dq = (TOPO == kRope) ? d3[eq][c] : D[c * NM + q];
+                    const float lq = (TOPO == kRope) ? l3[eq][c] : DL[c * NM + q];
+                    e0[c] = (xq - x[k][c]) + (dq - d[k][c]);
+                    de[c] = lq - sp[c];
                     e1[c] = e0[c] + de[c];
                     sm[c] = e1[c] + e0[c];
                 }
@@ -701,9 +717,9 @@ struct Solver {
                 if (p >= 1 && p <= n - 2) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const float k0 = (X[c * NM + p - 1] - 2.f * X[c * NM + p] + X[c * NM + p + 1]) +
-                                         (D[c * NM + p - 1] - 2.f * D[c * NM + p] + D[c * NM + p + 1]);
-                        const float dk = DL[c * NM + p - 1] - 2.f * DL[c * NM + p] + DL[c * NM + p + 1];
+                        const float k0 = (x3[0][c] - 2.f * x3[1][c] + x3[2][c]) +
+                                         (d3[0][c] - 2.f * d3[1][c] + d3[2][c]);
+                        const float dk = l3[0][c] - 2.f * l3[1][c] + l3[2][c];
                         acc += 0.5f * kb * dk * (2.f * k0 + dk);
                     }
                 }
