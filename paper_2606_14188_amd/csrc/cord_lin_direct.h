@@ -125,51 +125,63 @@ __device__ __forceinline__ void sym_to_full(const float s[6], float m[3][3]) {
 
 // Banded Cholesky (half-bandwidth 8) by one wavefront, in place:
 // C[k][m-1] = A(k+m, k) -> L(k+m, k),  Dg[k] = A(k, k) -> 1 / L(k, k).
-// Right-looking: step k scales column k (lanes 1..8) and applies the rank-1
-// update to the 36 entries of the trailing 8x8 window (one lane each).  All
-// LDS reads of a step are issued together before any of its writes (the
-// entries a step updates are not read again within the step), so a step
-// costs one LDS round trip; steps depend on each other only through LDS,
-// whose reads and writes a wavefront performs in program order.  Lanes with
-// nothing to write at a step write to their own slot of `sink` (64 floats of
-// LDS not in use during the factorization) instead of branching, and every
-// lane reads its target at an address inside the workgroup's LDS.  The
-// pivot's inverse square root is the hardware approximation (within 1 ulp).
-// Rows past N act as identity rows.  Returns false if a pivot was not
-// positive (it is then replaced by 1 so that the sweeps stay finite).
+// Right-looking; at step k every lane has one job and writes one value:
+// lanes 0..35 apply the rank-1 update to one of the 36 entries of the
+// trailing 8x8 window, lanes 36..43 scale one entry of column k, lane 44
+// stores the pivot's inverse square root, the others write to their own
+// slot of `sink` (64 floats of LDS not in use during the factorization).
+// All LDS reads of a step (at addresses inside the workgroup's LDS for
+// every lane) are issued before its write, and the entries a step writes
+// are not read again within it, so a step costs one LDS round trip; steps
+// depend on each other only through LDS, whose reads and writes a
+// wavefront performs in program order.  The pivot's inverse square root is
+// the hardware approximation (within 1 ulp).  Rows past N act as identity
+// rows.  Returns false if a pivot was not positive (it is then replaced by
+// 1 so that the sweeps stay finite).
 __device__ __forceinline__ bool band_cholesky(float* C, float* Dg, int N, float* sink) {
     const int lane = (int)threadIdx.x & 63;
     // lanes 0..35 -> (a, b), 1 <= a <= b <= 8, column-major over b
-    int ua = 0, ub = 0;
-    {
+    int ua = 1, ub = 1;
+    if (lane < 36) {
         int idx = lane, b = 1;
         while (b <= kBand && idx >= b) { idx -= b; ++b; }
         ub = b;
         ua = idx + 1;
     }
     const bool upd = lane < 36;
-    const bool scl = lane >= 1 && lane <= kBand;
-    // update target of this lane, relative to step k: Dg[k + a] or C[k + a][b - a - 1]
-    // (lanes 36..63 point into C at rows up to 28 past k: inside the LDS
-    // that follows C, read and never written)
+    const bool scl = lane >= 36 && lane < 36 + kBand;
+    const bool piv = lane == 36 + kBand;
+    const int sm = scl ? lane - 35 : 0;   // column entry m of a scaling lane
+    // per-lane offsets relative to step k (floats): reads xa, xb from column
+    // k, t from the update target; the write goes to w (stride ws) or sink
+    const int ra = upd ? ua - 1 : (scl ? sm - 1 : 0);
+    const int rb = upd ? ub - 1 : ra;
     float* const tgt0 = (ua == ub) ? Dg + ua : C + ua * 8 + (ub - ua) - 1;
     const int tstride = (ua == ub) ? 1 : 8;
-    const int ca = upd ? ua - 1 : 0, cb = upd ? ub - 1 : 0, cm = scl ? lane - 1 : 0;
+    float* const t0 = upd ? tgt0 : Dg;
+    const int ts = upd ? tstride : 1;
+    float* const w0 = upd ? tgt0 : (scl ? C + sm - 1 : Dg);
+    const int ws = upd ? tstride : (scl ? 8 : 1);
+    const int lim = upd ? ub : (scl ? sm : 0);   // the write is real while k + lim < N
     float* const sk = sink + lane;
+    const float fu = upd ? 1.f : 0.f, fs = scl ? 1.f : 0.f, fp = piv ? 1.f : 0.f;
     bool ok = true;
     for (int k = 0; k < N; ++k) {
-        const bool live = upd && k + ub < N;
-        float* const tgt = tgt0 + k * tstride;
         float d = Dg[k];
-        const float xa = C[k * 8 + ca], xb = C[k * 8 + cb], xm = C[k * 8 + cm];
-        const float tv = *tgt;
+        const float xa = C[k * 8 + ra], xb = C[k * 8 + rb];
+        const float tv = t0[k * ts];
         __builtin_amdgcn_wave_barrier();
         ok = ok && (d > 0.f);
         d = d > 0.f ? d : 1.f;
         const float is = __builtin_amdgcn_rsqf(d);
-        *(scl ? C + k * 8 + lane - 1 : sk) = (k + lane < N) ? xm * is : 0.f;
-        *(lane == 0 ? Dg + k : sk) = is;
-        *(live ? tgt : sk) = tv - (xa * is) * (xb * is);
+        const bool live = (upd || scl || piv) && (k + lim < N || scl);
+        // every lane evaluates all three values and keeps its own with 0/1
+        // weights (finite operands: no branch, the kept value is exact)
+        const float pa = xa * is;
+        const float vu = tv - pa * (xb * is);
+        const float vs = (k + sm < N) ? pa : 0.f;
+        const float val = fu * vu + (fs * vs + fp * is);
+        *(live ? w0 + k * ws : sk) = val;
         __builtin_amdgcn_wave_barrier();
     }
     return ok;
