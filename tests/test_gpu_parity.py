@@ -343,6 +343,35 @@ def test_linearize_scratch_and_in_place_agree(monkeypatch):
         assert ea <= JAC_TOL and eb <= JAC_TOL
 
 
+def test_linearize_concurrent_streams():
+    """Two simulators linearizing at the same time on two streams (each with
+    its own scratch table; workgroups of both kernels share the CUs and the
+    hardware slots) give bitwise the results of running them one after the
+    other."""
+    import torch
+    ia = W.small_rope_batch(48, 64, 12, seed=495)
+    ib = W.small_rope_batch(40, 50, 16, seed=496)
+    runs = []
+    for insts in (ia, ib):
+        sim, s0, u, traj, st = _run(insts)
+        assert (st == 0).all()
+        runs.append((sim, u, traj))
+    ref = []
+    for sim, u, traj in runs:
+        A, Bm, _ = sim.linearize(traj, u)
+        torch.cuda.synchronize()
+        ref.append((A.clone(), Bm.clone()))
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    out = []
+    torch.cuda.synchronize()
+    for (sim, u, traj), sm in zip(runs, streams):
+        with torch.cuda.stream(sm):
+            out.append(sim.linearize(traj, u)[:2])
+    torch.cuda.synchronize()
+    for (A1, B1), (A2, B2) in zip(ref, out):
+        assert torch.equal(A1, A2) and torch.equal(B1, B2)
+
+
 def test_c2_linearize_full_size_sampled():
     """Dense A_t/B_t for the full 1024 x 64-node x 100-step rope batch in one
     launch (60 GB of A_t), sampled (instance, step) blocks against the oracle."""
