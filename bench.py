@@ -30,8 +30,8 @@ sys.path.insert(0, ROOT)
 FP32_PEAK_TFLOPS = 157.3        # MI355X FP32 vector, published
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
 
-# Algorithmic FP32 operations per particle, counted from the kernel source
-# ("Algorithmic work"): per conjugate-gradient iteration,
+# Algorithmic FP32 operations per particle, counted from the kernel source:
+# per conjugate-gradient iteration,
 # per Newton iteration (gradient + Hessian data + preconditioner + line
 # search), per interior-point iteration (residuals, right-hand side, step
 # rule) and per solved step (predictor, contacts, output).
