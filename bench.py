@@ -10,9 +10,11 @@ whole hot path over that batch:
   2. adjoint of a terminal cotangent -> s0_bar, u_bar   cord_rollout_backward
   3. dense A_t (384 x 384) and B_t (384 x 3), all t     cord_linearize
 
+Steps 2 and 3 read only the rollout's output; by default they run one after
+the other on one stream (--overlap runs them concurrently on two streams).
 value = particle-steps (sum n T) per second of that whole pass.  Inputs are
 resident in HBM before timing starts.  Per-kernel durations come from HIP
-events recorded on the stream the kernels run on (torch's current stream).
+events recorded on the stream each kernel runs on.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -354,6 +356,10 @@ def main():
     ap.add_argument("--grasp", default="dirichlet", choices=["dirichlet", "penalty"],
                     help="grasp of the rope batch (penalty: holonomic penalty with smoothed activation)")
     ap.add_argument("--no-serve", action="store_true", help="skip the short planning-stream leg")
+    ap.add_argument("--overlap", action="store_true",
+                    help="run the adjoint and the linearization concurrently on two streams, both after "
+                         "the rollout (default: one after the other on one stream, so that each kernel's "
+                         "duration, and the roofline fraction, is its own)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); instances are independent "
@@ -392,6 +398,15 @@ def main():
     sim = Sim(insts)
     if not args.no_aux:
         sim.use_aux(True)      # the adjoint and linearize reuse the rollout's step internals
+    overlap = with_lin and args.overlap
+    # The adjoint and the linearization both read only the rollout's output,
+    # so they run concurrently: the linearization through a second simulator
+    # over the same instances (a simulator serves one stream at a time) that
+    # shares the step internals, on a second stream of default priority.
+    sim_lin = Sim(insts) if overlap else sim
+    if overlap and not args.no_aux:
+        sim_lin.use_aux(True, buffer=sim.aux)
+    lin_stream = torch.cuda.Stream() if overlap else None
     dev = sim.device
     s0 = sim.pack_states([i.s0 for i in insts])
     u = sim.pack_controls([i.u for i in insts])
@@ -405,23 +420,40 @@ def main():
     ev = {k: [] for k in ("rollout", "backward", "linearize")}
 
     def one_step(record):
-        marks = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
+        # marks: rollout start/end, backward end (main stream); linearize
+        # start/end (on the stream it runs on)
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if record else None
+        main = torch.cuda.current_stream()
         if record:
             marks[0].record()
         sim.rollout(s0, u, out=traj, status=status)
         if record:
             marks[1].record()
+        if overlap:
+            lin_stream.wait_stream(main)          # trajectory and step internals written
+            with torch.cuda.stream(lin_stream):
+                if record:
+                    marks[3].record()
+                sim_lin.linearize(traj, u, A=A, Bm=Bm)
+                if record:
+                    marks[4].record()
         sim.backward(u, traj, sT_bar=sT)
         if record:
             marks[2].record()
-        if with_lin:
+        if with_lin and not overlap:
             sim.linearize(traj, u, A=A, Bm=Bm)
+            if record:
+                marks[4].record()
+            marks_lin0 = marks[2] if record else None
+        else:
+            marks_lin0 = marks[3] if record else None
+        if overlap:
+            main.wait_stream(lin_stream)          # the next rollout overwrites both
         if record:
-            marks[3].record()
             ev["rollout"].append((marks[0], marks[1]))
             ev["backward"].append((marks[1], marks[2]))
             if with_lin:
-                ev["linearize"].append((marks[2], marks[3]))
+                ev["linearize"].append((marks_lin0, marks[4]))
 
     for _ in range(args.warmup):
         one_step(False)
@@ -488,7 +520,9 @@ def main():
         "config": {"workload": "rope-64 x 1024, T=100, dt=0.005, 3 spheres + ground: forward + adjoint"
                                + (" + dense A_t/B_t" if with_lin else "")
                                + (", penalty grasp" if args.grasp == "penalty" else ""),
-                   "batch": B, "nodes": n, "horizon": T},
+                   "batch": B, "nodes": n, "horizon": T,
+                   "schedule": ("rollout, then adjoint and linearization concurrently on two streams" if overlap
+                                else "rollout, adjoint, linearization on one stream")},
         "kernel_ms": kern_ms,
         "kernel_roofline": {k: dict(v, frac=v["achieved"] / v["peak"]) for k, v in kernels.items()},
         "status_nonzero": int((st != 0).sum()),

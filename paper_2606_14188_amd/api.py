@@ -166,17 +166,31 @@ class Sim:
         return (A if dense else None), (Bm if want_B else None), out
 
     # ------------------------------------------------------------ step internals
-    def use_aux(self, on: bool = True):
+    def use_aux(self, on: bool = True, buffer=None):
         """Keep the internals of every solved step (cord_sim_set_aux): FULL
         rollouts write them, backward (FULL) and linearize read them instead
-        of solving each step again.  The buffer is owned by this object."""
+        of solving each step again.  The buffer is allocated here, or is
+        `buffer` (a float32 device tensor of at least info.aux_floats
+        floats, e.g. another simulator's `aux` over the same instances, so
+        that one simulator's rollout feeds the other's derivatives)."""
         if on:
-            if getattr(self, "_aux", None) is None:
+            if buffer is not None:
+                if (buffer.dtype != torch.float32 or buffer.device != self.device or not buffer.is_contiguous()
+                        or buffer.numel() < self.info.aux_floats):
+                    raise ValueError(f"aux buffer must be a contiguous float32 tensor on {self.device} "
+                                     f"with at least {self.info.aux_floats} elements")
+                self._aux = buffer
+            elif getattr(self, "_aux", None) is None:
                 self._aux = self._empty(max(self.info.aux_floats, 1))
             L.check(self.lib.cord_sim_set_aux(self._h, _ptr(self._aux)))
         else:
             L.check(self.lib.cord_sim_set_aux(self._h, None))
             self._aux = None
+
+    @property
+    def aux(self):
+        """The step-internals buffer in use (None if none)."""
+        return getattr(self, "_aux", None)
 
     # ------------------------------------------------------------ launch
     def set_launch(self, mode: int):

@@ -372,6 +372,44 @@ def test_linearize_concurrent_streams():
         assert torch.equal(A1, A2) and torch.equal(B1, B2)
 
 
+def test_backward_and_linearize_overlap_on_two_sims():
+    """The adjoint and the linearization of one rollout run at the same time
+    on two streams through two simulators over the same instances that share
+    the step-internals buffer; the results are bitwise those of running both
+    on one simulator one after the other."""
+    import torch
+    from paper_2606_14188_amd import Sim
+    insts = W.small_rope_batch(40, 64, 12, seed=497)
+    rng = np.random.default_rng(498)
+    sim = Sim(insts)
+    sim.use_aux(True)
+    sim_lin = Sim(insts)
+    sim_lin.use_aux(True, buffer=sim.aux)
+    s0 = sim.pack_states([i.s0 for i in insts])
+    u = sim.pack_controls([i.u for i in insts])
+    sT = sim.pack_states([rng.normal(size=i.n_s) for i in insts])
+    st = torch.zeros(len(insts), dtype=torch.int32, device=sim.device)
+    traj = sim.rollout(s0, u, status=st)
+    s0b, ub = sim.backward(u, traj, sT_bar=sT)
+    A, Bm, _ = sim.linearize(traj, u)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    ref = [t.clone() for t in (traj, s0b, ub, A, Bm)]
+    main, side = torch.cuda.current_stream(), torch.cuda.Stream()
+    for _ in range(2):
+        traj2 = sim.rollout(s0, u)
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            A2, B2, _ = sim_lin.linearize(traj2, u)
+        s0b2, ub2 = sim.backward(u, traj2, sT_bar=sT)
+        main.wait_stream(side)
+        torch.cuda.synchronize()
+        for nm, a, b in zip(["traj", "s0_bar", "u_bar", "A", "B"], ref, (traj2, s0b2, ub2, A2, B2)):
+            assert torch.equal(a, b), nm
+    with pytest.raises(ValueError):
+        sim_lin.use_aux(True, buffer=sim.aux[:10])
+
+
 def test_c2_linearize_full_size_sampled():
     """Dense A_t/B_t for the full 1024 x 64-node x 100-step rope batch in one
     launch (60 GB of A_t), sampled (instance, step) blocks against the oracle."""
