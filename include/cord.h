@@ -211,7 +211,11 @@ int cord_sim_info(const cord_sim* sim, cord_sim_info_t* out);
  * the trajectory written by the last such rollout.  The derivatives are
  * then evaluated at exactly the state the rollout solved; without the
  * buffer the step is solved again (in the adjoint kernel with the same
- * arithmetic, in the linearization kernels up to FP32 rounding).
+ * arithmetic, in the linearization kernels up to FP32 rounding).  One
+ * buffer may be set on several simulators created from the same instance
+ * descriptors: one simulator's rollout then feeds the others' adjoint or
+ * linearization, e.g. on another stream; the caller orders those calls
+ * (the readers after the rollout, the next rollout after the readers).
  * Errors: CORD_EINVAL (NULL sim).
  */
 int cord_sim_set_aux(cord_sim* sim, float* aux);
