@@ -51,7 +51,7 @@ def _create(descs):
 @pytest.mark.parametrize("field,value,code", [
     ("dt", 0.0, 1), ("gamma", 1.5, 1), ("kappa_bwd", 0.0, 1), ("kappa_fwd", -1.0, 1),
     ("mu", 0.3, 4), ("T", 0, 1), ("mass", 0.0, 1), ("ny", 2, 1), ("grip", 99, 1),
-    ("nspheres", 5, 1), ("n_inst0", 0, 1),
+    ("nspheres", 5, 1), ("n_inst0", 0, 1), ("nx", 0, 1), ("nx", 257, 4),
 ])
 def test_validation_errors(field, value, code):
     from paper_2606_14188_amd.api import make_desc
@@ -94,6 +94,13 @@ def test_too_many_obstacles_unsupported():
     d = make_desc(inst)
     rc, msg = _create([d])
     assert rc == 4 and "obstacles" in msg
+
+
+def test_cloth_beyond_the_largest_size_class_is_unsupported():
+    from paper_2606_14188_amd.api import make_desc
+    L, _ = _lib()
+    rc, msg = _create([make_desc(W.small_cloth_batch(1, 49, 48, 2, seed=5)[0])])
+    assert rc == L.CORD_EUNSUPPORTED and "exceed" in msg
 
 
 def test_null_arguments():

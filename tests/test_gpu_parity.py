@@ -110,6 +110,32 @@ def test_cloth_backward():
     _backward_parity(insts)
 
 
+def test_degenerate_and_largest_ropes():
+    """Ropes at the edges of what the simulator accepts, side by side in one
+    ragged batch: a single free particle (no spring, no gripper, no
+    controls) that falls onto the ground, ropes of two and three nodes (one
+    spring; one bending centre), and a rope of 256 nodes (the largest size
+    class).  States and gradients against the oracle."""
+    import torch
+    part = W.rope(1, T=30, grip_nodes=(), k=0.0, k_bend=0.0, h=0.01,
+                  s0=np.array([0.1, 0.2, 0.004, 0.3, -0.1, -0.5]))
+    insts = ([part] + W.small_rope_batch(1, 2, 20, seed=611) + W.small_rope_batch(1, 3, 20, seed=612)
+             + W.small_rope_batch(1, 256, 6, seed=613))
+    sim, s0, u, traj, st = _run(insts)
+    assert (st == 0).all(), st
+    _check_states(sim, traj, insts)
+    cots = [W.random_cotangent(i.n_s, 960 + j) for j, i in enumerate(insts)]
+    s0b, ub = sim.backward(u, traj, sT_bar=sim.pack_states(cots))
+    torch.cuda.synchronize()
+    s0bp, ubp = sim.split(s0b, "s"), sim.split(ub, "u")
+    for j, inst in enumerate(insts):
+        s0r, ur = rollout_backward(inst, orollout(inst)[0], sT_bar=cots[j])
+        es = rel_l2(s0bp[j], s0r)
+        eu = rel_l2(ubp[j], ur) if inst.n_u else 0.0
+        print(f"instance {j} (rope n={inst.n}): grad err u {eu:.2e} s0 {es:.2e}", flush=True)
+        assert es <= GRAD_TOL and eu <= GRAD_TOL
+
+
 def test_checkpointed_backward_bitwise():
     import torch
     from paper_2606_14188_amd import _lib as L
