@@ -123,9 +123,12 @@ typedef struct {
  *   kind      CORD_ROPE: nx nodes in a chain (ny must be 1), stretch springs
  *             between neighbours (stiffness k_struct, rest h) and a
  *             discrete-curvature bending term 1/2 k_bend |x_a - 2x_b + x_c|^2.
+ *             1 <= nx <= 256 (nx = 1: a single particle).
  *             CORD_CLOTH: nx*ny grid, node (ix, iy) has index iy*nx + ix;
  *             structural (k_struct, rest h), shear (k_shear, rest h*sqrt 2)
  *             and bend springs two nodes apart (k_bend, rest 2h).
+ *             nx, ny >= 2 and nx*ny <= 2304.  Larger instances:
+ *             CORD_EUNSUPPORTED.
  *   T         horizon (number of steps), >= 1
  *   mass      lumped mass of every node [kg], > 0
  *   grip_node node held by gripper k, distinct, in [0, n)
