@@ -178,10 +178,14 @@ def test_nonfinite_input_flags_only_that_instance():
     assert st[1] == 4 and st[0] == 0 and st[2] == 0, st
 
 
-@pytest.mark.parametrize("kind", ["rope", "cloth"])
+@pytest.mark.parametrize("kind", ["rope", "rope_tiny", "cloth"])
 def test_linearize_dense(kind):
     import torch
-    if kind == "rope":
+    if kind == "rope_tiny":
+        # ropes whose free DoFs (3, 6, 12) are fewer than the band is wide
+        insts = (W.small_rope_batch(1, 2, 3, seed=456) + W.small_rope_batch(1, 3, 3, seed=457)
+                 + W.small_rope_batch(1, 5, 2, seed=458))
+    elif kind == "rope":
         # one rope per size class of the direct kernel (32, 64, 128 nodes)
         # plus a ragged one; T differs so the (instance, step) grid is ragged
         insts = (W.small_rope_batch(1, 10, 4, seed=451) + W.small_rope_batch(1, 7, 4, seed=452)
