@@ -110,6 +110,18 @@ def test_cloth_backward():
     _backward_parity(insts)
 
 
+def test_smallest_cloths():
+    """Cloths of 2x2, 3x2 and 2x5 nodes (two corners gripped, so two to
+    eight free particles; no bend springs along a side of two nodes):
+    states and gradients against the oracle."""
+    insts = (W.small_cloth_batch(1, 2, 2, 12, seed=492) + W.small_cloth_batch(1, 3, 2, 12, seed=502)
+             + W.small_cloth_batch(1, 2, 5, 12, seed=495))
+    sim, s0, u, traj, st = _run(insts)
+    assert (st == 0).all(), st
+    _check_states(sim, traj, insts)
+    _backward_parity(insts)
+
+
 def test_degenerate_and_largest_ropes():
     """Ropes at the edges of what the simulator accepts, side by side in one
     ragged batch: a single free particle (no spring, no gripper, no
