@@ -127,12 +127,13 @@ def test_degenerate_and_largest_ropes():
     ragged batch: a single free particle (no spring, no gripper, no
     controls) that falls onto the ground, ropes of two and three nodes (one
     spring; one bending centre), and a rope of 256 nodes (the largest size
-    class).  States and gradients against the oracle."""
+    class), and a horizon of one step.  States and gradients against the
+    oracle."""
     import torch
     part = W.rope(1, T=30, grip_nodes=(), k=0.0, k_bend=0.0, h=0.01,
                   s0=np.array([0.1, 0.2, 0.004, 0.3, -0.1, -0.5]))
     insts = ([part] + W.small_rope_batch(1, 2, 20, seed=611) + W.small_rope_batch(1, 3, 20, seed=612)
-             + W.small_rope_batch(1, 256, 6, seed=613))
+             + W.small_rope_batch(1, 256, 6, seed=613) + W.small_rope_batch(1, 20, 1, seed=614))
     sim, s0, u, traj, st = _run(insts)
     assert (st == 0).all(), st
     _check_states(sim, traj, insts)
@@ -195,8 +196,9 @@ def test_linearize_dense(kind):
     import torch
     if kind == "rope_tiny":
         # ropes whose free DoFs (3, 6, 12) are fewer than the band is wide
+        # (and a horizon of one step)
         insts = (W.small_rope_batch(1, 2, 3, seed=456) + W.small_rope_batch(1, 3, 3, seed=457)
-                 + W.small_rope_batch(1, 5, 2, seed=458))
+                 + W.small_rope_batch(1, 5, 2, seed=458) + W.small_rope_batch(1, 33, 1, seed=459))
     elif kind == "rope":
         # one rope per size class of the direct kernel (32, 64, 128 nodes)
         # plus a ragged one; T differs so the (instance, step) grid is ragged
