@@ -313,6 +313,10 @@ typedef struct {
  * allocation fails the kernel works without it, at lower speed, with
  * bitwise the same results).  Linearize calls on one
  * simulator share that table: calls on different streams must not overlap.
+ * Environment: CORD_LINEARIZE_NO_SCRATCH=1 (read at every call) runs the
+ * direct kernel without the table (bitwise the same results);
+ * CORD_LINEARIZE_ITERATIVE=1 (read once per process) uses the row-by-row
+ * kernel for every instance (the same derivatives up to FP32 rounding).
  * Errors: CORD_EINVAL if A, Bm and jvp are all NULL.
  */
 int cord_linearize(cord_sim* sim, const float* traj, const float* u, float* A, float* Bm,
