@@ -65,6 +65,13 @@ def _oracle_job(args):
     return time.perf_counter() - t0, inst.n * inst.T
 
 
+def _one_thread():
+    # one BLAS / OpenMP thread per worker process, so that `cores` is the
+    # number of threads the baseline used (set before numpy is imported)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+
+
 def cpu_baseline(workers: int, per_worker: int, T: int, with_lin: bool):
     """The FP64 oracle on a bounded sample of the same workload: `workers`
     processes, each running `per_worker` instances (forward, adjoint and
@@ -73,13 +80,14 @@ def cpu_baseline(workers: int, per_worker: int, T: int, with_lin: bool):
     import multiprocessing as mp
     jobs = [(i, 1024, 64, T, with_lin) for i in range(workers * per_worker)]
     t0 = time.perf_counter()
-    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"),
+                                initializer=_one_thread) as ex:
         res = list(ex.map(_oracle_job, jobs))
     wall = time.perf_counter() - t0
     ps = sum(r[1] for r in res)
     return {"value": ps / wall, "unit": "particle-steps/s", "cores": workers, "kind": "oracle",
             "sample": f"{len(jobs)} of the 1024 ropes (64 nodes), first {T} steps, forward + adjoint"
-                      f"{' + dense A/B' if with_lin else ''}, {workers} processes, {wall:.1f} s wall"}
+                      f"{' + dense A/B' if with_lin else ''}, {workers} single-threaded processes, {wall:.1f} s wall"}
 
 
 # ---------------------------------------------------------------- other workloads
