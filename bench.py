@@ -86,7 +86,7 @@ def cpu_baseline(workers: int, per_worker: int, T: int, with_lin: bool):
     wall = time.perf_counter() - t0
     ps = sum(r[1] for r in res)
     return {"value": ps / wall, "unit": "particle-steps/s", "cores": workers, "kind": "oracle",
-            "sample": f"{len(jobs)} of the 1024 ropes (64 nodes), first {T} steps, forward + adjoint"
+            "sample": f"{len(jobs)} of the 1024 ropes (64 nodes), {T} of 100 steps, forward + adjoint"
                       f"{' + dense A/B' if with_lin else ''}, {workers} single-threaded processes, {wall:.1f} s wall"}
 
 
@@ -354,7 +354,7 @@ def main():
     ap.add_argument("--no-linearize", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-workers", type=int, default=8)
     ap.add_argument("--cpu-per-worker", type=int, default=1)
-    ap.add_argument("--cpu-T", type=int, default=25)
+    ap.add_argument("--cpu-T", type=int, default=100)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "probe", "copy"])
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
