@@ -407,10 +407,11 @@ def main():
     if not args.no_aux:
         sim.use_aux(True)      # the adjoint and linearize reuse the rollout's step internals
     overlap = with_lin and args.overlap
-    # The adjoint and the linearization both read only the rollout's output,
-    # so they run concurrently: the linearization through a second simulator
-    # over the same instances (a simulator serves one stream at a time) that
-    # shares the step internals, on a second stream of default priority.
+    # The adjoint and the linearization both read only the rollout's output.
+    # With --overlap they run concurrently: the linearization through a
+    # second simulator over the same instances (a simulator serves one stream
+    # at a time) that shares the step internals, on a second stream of
+    # default priority.
     sim_lin = Sim(insts) if overlap else sim
     if overlap and not args.no_aux:
         sim_lin.use_aux(True, buffer=sim.aux)
