@@ -8,7 +8,7 @@ import pytest
 import workloads as W
 from oracle.derivatives import StepDerivative, rollout_backward
 from oracle.step import rollout as orollout
-from tests.parity import GRAD_TOL, JAC_TOL
+from tests.parity import GRAD_TOL, JAC_TOL, STATE_TOL, state_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -62,6 +62,48 @@ def test_first_gradient_step_and_costs_match_oracle():
         print("costs gpu", r.costs, "oracle", ref_costs)
         np.testing.assert_allclose(r.costs, ref_costs, rtol=2e-4)
         assert r.best == int(np.argmin(ref_costs))
+        srv.release(t)
+    finally:
+        srv.close()
+
+
+def test_plan_after_several_gradient_steps_matches_oracle():
+    """Four projected gradient steps from caller-given candidates (so no
+    random draw is involved): every candidate's final cost, the winner and
+    the winner's controls and trajectory against the oracle run through the
+    same steps."""
+    from paper_2606_14188_amd.serve import Server
+    inst = _rope(n=30, T=8, seed=905)
+    rng = np.random.default_rng(5)
+    C, iters, step, umax, reg = 5, 4, 5.0, 0.5, 1e-3
+    u_init = inst.u[None] + 0.2 * rng.normal(size=(C,) + inst.u.shape)
+    srv = Server(hbm_budget=1 << 30, max_slots=2)
+    try:
+        t = srv.submit(inst, goal_node=inst.n - 1, goal=GOAL, n_cand=C, iters=iters, step=step, u_max=umax,
+                       u_reg=reg, u_init=u_init)
+        r = srv.wait(t, 120000)
+        assert r is not None and r.status == 0 and r.sim_status == 0
+        ref_u, ref_costs, ref_traj = [], [], []
+        for c in range(C):
+            uc = u_init[c].copy()
+            for _ in range(iters):
+                uc, _ = _oracle_step(inst, uc, inst.n - 1, GOAL, step, umax, reg)
+            jc, tr = _cost(inst, uc, inst.n - 1, GOAL, reg)
+            ref_u.append(uc)
+            ref_costs.append(jc)
+            ref_traj.append(tr)
+        ref_costs = np.array(ref_costs)
+        print("costs gpu", r.costs, "oracle", ref_costs, flush=True)
+        np.testing.assert_allclose(r.costs, ref_costs, rtol=2e-4)
+        # the winner is a minimiser of the oracle's costs (to the same
+        # tolerance; near-ties may resolve either way)
+        b = r.best
+        assert ref_costs[b] <= ref_costs.min() * (1 + 2e-4)
+        eu = np.linalg.norm(r.u - ref_u[b]) / np.linalg.norm(ref_u[b] - u_init[b])
+        print(f"winner {b}: controls err (relative to the distance moved) {eu:.2e}", flush=True)
+        assert eu <= GRAD_TOL
+        ex, ev = state_errors(r.traj, ref_traj[b], inst.n)
+        assert ex <= STATE_TOL and ev <= STATE_TOL, (ex, ev)
         srv.release(t)
     finally:
         srv.close()
