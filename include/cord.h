@@ -389,8 +389,12 @@ int cord_sim_classes(const cord_sim* sim, int32_t* topo, int32_t* nmax, int32_t*
  *     J(u) = |x_T[goal_node] - goal|^2 + u_reg * sum_t |u_t|^2,
  * each step being a batched forward rollout and adjoint of all candidates
  * (cord_rollout / cord_rollout_backward).  Candidate 0 starts from u_warm,
- * candidate c > 0 from u_warm + sigma * N(0, 1) (SplitMix64 + Box-Muller from
- * `seed`) unless u_init gives all starts explicitly.  After the last step the
+ * candidate c > 0 from u_warm + sigma * N(0, 1) unless u_init gives all
+ * starts explicitly.  The normal values come from SplitMix64 seeded with
+ * `seed`, two outputs per value, candidate by candidate and then in u's
+ * order: each output maps to a = ((x >> 11) + 1/2) 2^-53 in (0, 1), and
+ * z = sqrt(-2 ln a1) cos(2 pi a2) (Box-Muller, in double), rounded to
+ * float; the start is the float sum u_warm + sigma * z.  After the last step the
  * candidates are rolled out once more, the lowest J wins (ties: lowest
  * index), and for want_AB the dense A_t, B_t along the winner are computed
  * (cord_linearize).  All of this runs on the device without host round trips;

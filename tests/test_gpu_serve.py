@@ -8,6 +8,7 @@ import pytest
 import workloads as W
 from oracle.derivatives import StepDerivative, rollout_backward
 from oracle.step import rollout as orollout
+from tests.draws import candidate_starts
 from tests.parity import GRAD_TOL, JAC_TOL, STATE_TOL, state_errors
 
 pytestmark = pytest.mark.gpu
@@ -105,6 +106,32 @@ def test_plan_after_several_gradient_steps_matches_oracle():
         ex, ev = state_errors(r.traj, ref_traj[b], inst.n)
         assert ex <= STATE_TOL and ev <= STATE_TOL, (ex, ev)
         srv.release(t)
+    finally:
+        srv.close()
+
+
+def test_seeded_candidates_follow_the_documented_generator():
+    """A request whose candidates the server draws from `seed` gives bitwise
+    the plan of the same request with those starts, drawn here from the
+    documented generator, passed as u_init (that plan is compared with the
+    oracle in the test above)."""
+    from paper_2606_14188_amd.serve import Server
+    inst = _rope(n=24, T=6, seed=907)
+    C, sigma, seed = 6, 0.05, 0x1234ABCD5678
+    starts = candidate_starts(inst.u, C, sigma, seed)
+    assert np.all(np.std(starts[1:] - starts[0], axis=(1, 2)) > 0.5 * sigma)
+    srv = Server(hbm_budget=1 << 30, max_slots=2)
+    try:
+        kw = dict(goal_node=inst.n - 1, goal=GOAL, n_cand=C, iters=2, step=1.0)
+        t1 = srv.submit(inst, sigma=sigma, seed=seed, u_warm=inst.u, **kw)
+        r1 = srv.wait(t1, 120000)
+        t2 = srv.submit(inst, u_init=starts, **kw)
+        r2 = srv.wait(t2, 120000)
+        assert r1.status == 0 and r2.status == 0
+        assert np.array_equal(r1.costs, r2.costs)
+        assert r1.best == r2.best and np.array_equal(r1.u, r2.u)
+        srv.release(t1)
+        srv.release(t2)
     finally:
         srv.close()
 
