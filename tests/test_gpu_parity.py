@@ -29,8 +29,10 @@ def _run(insts, **kw):
 
 
 def _check_states(sim, traj, insts, idx=None):
+    """States against the oracle; returns the oracle trajectories by index."""
     parts = sim.split(traj, "traj")
     idx = range(len(insts)) if idx is None else idx
+    refs = {}
     for i in idx:
         inst = insts[i]
         ref, st = orollout(inst)
@@ -38,6 +40,8 @@ def _check_states(sim, traj, insts, idx=None):
         ex, ev = state_errors(parts[i], ref, inst.n)
         print(f"instance {i} ({inst.kind} n={inst.n} T={inst.T}): state err x {ex:.2e} v {ev:.2e}", flush=True)
         assert ex <= STATE_TOL and ev <= STATE_TOL, (i, ex, ev)
+        refs[i] = ref
+    return refs
 
 
 def test_c1_forward_and_gradient():
@@ -290,12 +294,50 @@ def test_c2_full_size_sampled():
 
 
 def test_c3_full_size_sampled():
-    """C3 at full size (256 cloths of 32x32, 60 steps); one sampled instance."""
+    """C3 at full size (256 cloths of 32x32, 60 steps) in the launches the
+    cloth benchmark times: a full rollout keeping its step internals, the
+    checkpointed (every 10 steps) rollout and adjoint, and 6 JVP tangents
+    per step (unit control directions, the B_t columns).  One sampled
+    instance's states, gradient and tangents (three steps) against the
+    oracle."""
+    import torch
+    from paper_2606_14188_amd import Sim, _lib as L
     insts = W.config_c3()
-    sim, s0, u, traj, st = _run(insts)
-    print("status counts", np.bincount(st, minlength=5))
+    sim = Sim(insts)
+    sim.use_aux(True)
+    B, T = len(insts), insts[0].T
+    s0 = sim.pack_states([i.s0 for i in insts])
+    u = sim.pack_controls([i.u for i in insts])
+    st = torch.full((B,), -1, dtype=torch.int32, device=sim.device)
+    traj = sim.rollout(s0, u, status=st)
+    cots = [W.random_cotangent(i.n_s, 8000 + j) for j, i in enumerate(insts)]
+    ck = sim.rollout(s0, u, store=L.STORE_CKPT, ckpt_every=10)
+    s0b, ub = sim.backward(u, ck, sT_bar=sim.pack_states(cots), store=L.STORE_CKPT, ckpt_every=10)
+    k = 6
+    du = np.zeros((B, T, k, 6), np.float32)
+    du[:, :, np.arange(6), np.arange(6)] = 1.0
+    _, _, jv = sim.linearize(traj, u, dense=False, want_B=False, jvp_k=k,
+                             jvp_du=torch.from_numpy(du.ravel()).to(sim.device))
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    print("status counts", np.bincount(st, minlength=5), flush=True)
     assert (st == 0).all()
-    _check_states(sim, traj, insts, idx=[255])
+    j = 255
+    inst = insts[j]
+    ref = _check_states(sim, traj, insts, idx=[j])[j]
+    s0r, ur = rollout_backward(inst, ref, sT_bar=cots[j])
+    es, eu = rel_l2(sim.split(s0b, "s")[j], s0r), rel_l2(sim.split(ub, "u")[j], ur)
+    print(f"instance {j}: grad err u {eu:.2e} s0 {es:.2e}", flush=True)
+    assert es <= GRAD_TOL and eu <= GRAD_TOL
+    ns, n3 = inst.n_s, 3 * inst.n
+    blk = jv.cpu().numpy()[j * T * k * ns:(j + 1) * T * k * ns].reshape(T, k, ns)
+    tr = sim.split(traj, "traj")[j].reshape(T + 1, ns).astype(np.float64)
+    for t in (0, 29, 59):
+        d = StepDerivative(inst, tr[t], inst.u[t], inst.kappa_bwd)
+        dxn, dvn = d.jvp(np.zeros((n3, k)), np.zeros((n3, k)), np.eye(6))
+        e = rel_l2(blk[t], np.vstack([dxn, dvn]).T)
+        print(f"instance {j} t={t}: jvp err {e:.2e}", flush=True)
+        assert e <= JAC_TOL
 
 
 def test_c1_linearize_in_contact():
