@@ -283,14 +283,41 @@ def test_autograd_function():
     assert torch.equal(s0.grad, s0b2) and torch.equal(u.grad, ub2)
 
 
-def test_c2_full_size_sampled():
-    """C2 at full size (1024 ropes of 64 nodes, 100 steps) in the launch the
-    benchmark times; four sampled instances against the oracle."""
+def _c2_bench_sim():
+    """The full-size rope batch as the benchmark runs it: step internals
+    kept by the rollout for the adjoint and the linearization."""
+    import torch
+    from paper_2606_14188_amd import Sim
     insts = W.config_c2()
-    sim, s0, u, traj, st = _run(insts)
+    sim = Sim(insts)
+    sim.use_aux(True)
+    s0 = sim.pack_states([i.s0 for i in insts])
+    u = sim.pack_controls([i.u for i in insts])
+    st = torch.full((len(insts),), -1, dtype=torch.int32, device=sim.device)
+    traj = sim.rollout(s0, u, status=st)
+    torch.cuda.synchronize()
+    return insts, sim, s0, u, traj, st.cpu().numpy()
+
+
+def test_c2_full_size_sampled():
+    """C2 at full size (1024 ropes of 64 nodes, 100 steps) in the launches
+    the benchmark times (rollout keeping its step internals, adjoint of the
+    benchmark's terminal cotangents); sampled instances' states and
+    gradients against the oracle."""
+    import torch
+    insts, sim, s0, u, traj, st = _c2_bench_sim()
     print("status counts", np.bincount(st, minlength=5))
     assert (st == 0).all()
-    _check_states(sim, traj, insts, idx=[0, 341, 682, 1023])
+    cots = [W.random_cotangent(i.n_s, 7000 + j) for j, i in enumerate(insts)]
+    s0b, ub = sim.backward(u, traj, sT_bar=sim.pack_states(cots))
+    torch.cuda.synchronize()
+    refs = _check_states(sim, traj, insts, idx=[0, 341, 682, 1023])
+    s0p, up = sim.split(s0b, "s"), sim.split(ub, "u")
+    for j in (0, 1023):
+        s0r, ur = rollout_backward(insts[j], refs[j], sT_bar=cots[j])
+        es, eu = rel_l2(s0p[j], s0r), rel_l2(up[j], ur)
+        print(f"instance {j}: grad err u {eu:.2e} s0 {es:.2e}", flush=True)
+        assert es <= GRAD_TOL and eu <= GRAD_TOL
 
 
 def test_c3_full_size_sampled():
@@ -498,10 +525,11 @@ def test_backward_and_linearize_overlap_on_two_sims():
 
 def test_c2_linearize_full_size_sampled():
     """Dense A_t/B_t for the full 1024 x 64-node x 100-step rope batch in one
-    launch (60 GB of A_t), sampled (instance, step) blocks against the oracle."""
+    launch (60 GB of A_t), with the step internals kept as the benchmark
+    runs it; sampled (instance, step) blocks against the oracle."""
     import torch
-    insts = W.config_c2()
-    sim, s0, u, traj, st = _run(insts)
+    insts, sim, s0, u, traj, st = _c2_bench_sim()
+    assert (st == 0).all()
     status = torch.zeros(len(insts), dtype=torch.int32, device=sim.device)
     A, Bm, _ = sim.linearize(traj, u, status=status)
     torch.cuda.synchronize()
