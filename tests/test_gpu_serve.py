@@ -136,6 +136,48 @@ def test_seeded_candidates_follow_the_documented_generator():
         srv.close()
 
 
+def test_full_size_request_sampled():
+    """A request of the planning stream's shape (rope of 88 nodes, 128
+    candidates, T = 30, 10 gradient steps of 0.05, A_t/B_t of the winner),
+    from caller-given candidates: the winner's and two other candidates'
+    final costs, the winner's controls and trajectory, and its A_t/B_t at
+    two steps against the oracle."""
+    from paper_2606_14188_amd.serve import Server
+    inst = _rope(n=88, T=30, seed=930)
+    rng = np.random.default_rng(9)
+    C, iters, step, umax, reg = 128, 10, 0.05, 0.5, 1e-3
+    u_init = inst.u[None] + 0.05 * rng.normal(size=(C,) + inst.u.shape)
+    srv = Server(hbm_budget=4 << 30, max_slots=2)
+    try:
+        t = srv.submit(inst, goal_node=inst.n - 1, goal=GOAL, n_cand=C, iters=iters, step=step, u_max=umax,
+                       u_reg=reg, u_init=u_init, want_AB=True)
+        r = srv.wait(t, 120000)
+        assert r is not None and r.status == 0 and r.sim_status == 0
+        b = r.best
+        assert r.costs[b] == r.costs.min()
+        for c in sorted({b, 0, 77}):
+            uc = u_init[c].copy()
+            for _ in range(iters):
+                uc, _ = _oracle_step(inst, uc, inst.n - 1, GOAL, step, umax, reg)
+            jc, tr = _cost(inst, uc, inst.n - 1, GOAL, reg)
+            print(f"candidate {c}: cost gpu {r.costs[c]:.8f} oracle {jc:.8f}", flush=True)
+            assert abs(r.costs[c] - jc) <= 2e-4 * abs(jc)
+            if c == b:
+                eu = np.linalg.norm(r.u - uc) / np.linalg.norm(uc - u_init[c])
+                ex, ev = state_errors(r.traj, tr, inst.n)
+                print(f"winner: controls err {eu:.2e}, state err x {ex:.2e} v {ev:.2e}", flush=True)
+                assert eu <= GRAD_TOL and ex <= STATE_TOL and ev <= STATE_TOL
+        for k in (0, 29):
+            Ar, Br = StepDerivative(inst, r.traj[k].astype(np.float64), r.u[k].astype(np.float64),
+                                    inst.kappa_bwd).dense()
+            ea = np.linalg.norm(r.A[k] - Ar) / np.linalg.norm(Ar)
+            eb = np.linalg.norm(r.B[k] - Br) / np.linalg.norm(Br)
+            assert ea <= JAC_TOL and eb <= JAC_TOL, (k, ea, eb)
+        srv.release(t)
+    finally:
+        srv.close()
+
+
 def test_winner_linearization_matches_oracle():
     from paper_2606_14188_amd.serve import Server
     inst = _rope(n=24, T=6, seed=910)
