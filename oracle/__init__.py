@@ -21,6 +21,7 @@ model        element lists, elastic energy and its first three derivatives
 sdf          signed distances, normals and curvatures of the obstacles
 step         one time step (stage 1 + stage 2) and rollouts
 derivatives  per-step JVP / VJP, dense A_t / B_t, rollout gradient
+planner      reference projected-gradient planner (cost, gradient, step, argmin)
 """
 STATUS_OK = 0
 STATUS_NEWTON_NOCONV = 1

@@ -201,6 +201,24 @@ def stage1(inst, el, lay, y0, xhat, max_iter=100, pen=None):
     return y, (STATUS_OK if ok else STATUS_NEWTON_NOCONV), it + 1
 
 
+def singular(P, rtol=1e-13):
+    """True if the exact Hessian P = dF/dy at y* is singular (to rtol).
+
+    The derivatives of eq. (diff-sim) need (dF/dq*)^{-1}; they exist
+    whenever P is nonsingular, positive definite or not.  Compression makes
+    P indefinite at a stationary point of Psi that is not a minimum (a
+    straight compressed rope), which is a valid root of F; only a singular
+    P leaves the step's derivative undefined.  Test: a sparse LU with
+    partial pivoting whose smallest pivot is below rtol times the largest
+    (or which reports an exactly singular factor)."""
+    try:
+        lu = spla.splu(sp.csc_matrix(P))
+    except RuntimeError:
+        return True
+    piv = np.abs(lu.U.diagonal())
+    return not (np.all(np.isfinite(piv)) and piv.min() > rtol * piv.max())
+
+
 def contact_pairs(inst, lay, y):
     """All (free node, obstacle) pairs with phi, n and SDF Hessian at y."""
     nodes, obs, phis, ns, Hs = [], [], [], [], []
@@ -334,11 +352,9 @@ def step(inst, x, v, u_t, kappa, el=None, lay=None, g=None) -> StepResult:
     gap = phi.copy()
     active = np.zeros(len(phi), dtype=bool)
     it2 = 0
+    if P.shape[0] and singular(P):
+        status = max(status, STATUS_NOT_PD)
     if len(phi):
-        try:
-            np.linalg.cholesky(P.toarray()) if P.shape[0] <= 1200 else None
-        except np.linalg.LinAlgError:
-            status = max(status, STATUS_NOT_PD)
         N = normal_matrix(lay, pn, nrm)
         D, lam, gap, it2, ok = interior_point(P, N, phi, kappa, fscale, xscale)
         if kappa <= 0.0:

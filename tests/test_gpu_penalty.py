@@ -8,7 +8,8 @@ import pytest
 import workloads as W
 from oracle.derivatives import StepDerivative, rollout_backward
 from oracle.step import rollout as orollout
-from tests.parity import GRAD_TOL, JAC_TOL, STATE_TOL, rel_l2, state_errors
+from tests.parity import (GRAD_TOL, JAC_TOL, STATE_TOL, check, gradient_block_errors, jacobian_block_errors,
+                          state_errors, tangent_block_errors)
 
 pytestmark = pytest.mark.gpu
 
@@ -66,9 +67,8 @@ def test_penalty_gradient():
     for i, inst in enumerate(insts):
         tr = tp[i].reshape(inst.T + 1, inst.n_s).astype(np.float64)
         sb_ref, ub_ref = rollout_backward(inst, tr, sT_bar=cot[i])
-        es, eu = rel_l2(sp[i], sb_ref), rel_l2(up[i], ub_ref)
-        print(f"{inst.kind} n={inst.n} {inst.grip_mode}: s0_bar err {es:.2e} u_bar err {eu:.2e}", flush=True)
-        assert es <= GRAD_TOL and eu <= GRAD_TOL
+        check(gradient_block_errors(sp[i], up[i], sb_ref, ub_ref, inst.n), GRAD_TOL,
+              f"{inst.kind} n={inst.n} {inst.grip_mode} gradient")
 
 
 def test_penalty_linearize_and_jvp():
@@ -98,10 +98,7 @@ def test_penalty_linearize_and_jvp():
         for t in sorted({0, inst.T // 2, inst.T - 1}):
             d = StepDerivative(inst, tr[t], inst.u[t], inst.kappa_bwd)
             Ar, Br = d.dense()
-            ea = np.linalg.norm(Aj[t] - Ar) / np.linalg.norm(Ar)
-            eb = np.linalg.norm(Bj[t] - Br) / np.linalg.norm(Br)
             ref = d.jvp_s(ds[j][t].T, du[j][t].T).T
-            ej = np.linalg.norm(blk[t] - ref) / np.linalg.norm(ref)
-            print(f"{inst.kind} n={inst.n} {inst.grip_mode} t={t}: A err {ea:.2e} B err {eb:.2e} jvp err {ej:.2e}",
-                  flush=True)
-            assert ea <= JAC_TOL and eb <= JAC_TOL and ej <= JAC_TOL
+            errs = jacobian_block_errors(Aj[t], Ar, Bj[t], Br, inst.n)
+            errs.update(tangent_block_errors(blk[t], ref, inst.n))
+            check(errs, JAC_TOL, f"{inst.kind} n={inst.n} {inst.grip_mode} t={t}")

@@ -6,10 +6,10 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle.derivatives import StepDerivative, rollout_backward
-from oracle.step import rollout as orollout
+from oracle import planner
+from oracle.derivatives import StepDerivative
 from tests.draws import candidate_starts
-from tests.parity import GRAD_TOL, JAC_TOL, STATE_TOL, state_errors
+from tests.parity import GRAD_TOL, JAC_TOL, STATE_TOL, check, jacobian_block_errors, state_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -21,20 +21,12 @@ def _rope(n=40, T=10, seed=900):
 
 
 def _oracle_step(inst, u0, goal_node, goal, step, u_max, reg):
-    tr, _ = orollout(inst.replace(u=u0))
-    n = inst.n
-    d = tr[-1, 3 * goal_node:3 * goal_node + 3] - goal
-    sb = np.zeros(6 * n)
-    sb[3 * goal_node:3 * goal_node + 3] = 2 * d
-    _, ub = rollout_backward(inst.replace(u=u0), tr, sT_bar=sb)
-    g = ub + 2 * reg * u0
-    return np.clip(u0 - step * g, -u_max, u_max), g
+    _, g, _ = planner.cost_gradient(inst, u0, goal_node, goal, reg)
+    return planner.projected_step(u0, g, step, u_max), g
 
 
 def _cost(inst, u, goal_node, goal, reg):
-    tr, _ = orollout(inst.replace(u=u))
-    d = tr[-1, 3 * goal_node:3 * goal_node + 3] - goal
-    return float(d @ d + reg * np.sum(u * u)), tr
+    return planner.cost(inst, u, goal_node, goal, reg)
 
 
 def test_first_gradient_step_and_costs_match_oracle():
@@ -170,9 +162,7 @@ def test_full_size_request_sampled():
         for k in (0, 29):
             Ar, Br = StepDerivative(inst, r.traj[k].astype(np.float64), r.u[k].astype(np.float64),
                                     inst.kappa_bwd).dense()
-            ea = np.linalg.norm(r.A[k] - Ar) / np.linalg.norm(Ar)
-            eb = np.linalg.norm(r.B[k] - Br) / np.linalg.norm(Br)
-            assert ea <= JAC_TOL and eb <= JAC_TOL, (k, ea, eb)
+            check(jacobian_block_errors(r.A[k], Ar, r.B[k], Br, inst.n), JAC_TOL, f"winner t={k}")
         srv.release(t)
     finally:
         srv.close()
@@ -190,9 +180,7 @@ def test_winner_linearization_matches_oracle():
         for k in range(inst.T):
             Ar, Br = StepDerivative(inst, r.traj[k].astype(np.float64), r.u[k].astype(np.float64),
                                     inst.kappa_bwd).dense()
-            ea = np.linalg.norm(r.A[k] - Ar) / np.linalg.norm(Ar)
-            eb = np.linalg.norm(r.B[k] - Br) / np.linalg.norm(Br)
-            assert ea <= JAC_TOL and eb <= JAC_TOL, (k, ea, eb)
+            check(jacobian_block_errors(r.A[k], Ar, r.B[k], Br, inst.n), JAC_TOL, f"winner t={k}")
         srv.release(t)
     finally:
         srv.close()
