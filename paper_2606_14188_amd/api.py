@@ -6,6 +6,7 @@ memory and the stream.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 from ctypes import POINTER, byref, c_int64, c_uint32, c_void_p
 
@@ -60,6 +61,16 @@ def make_desc(inst) -> L.InstanceDesc:
         d.grip_mode = L.GRIP_PENALTY
         d.D_max, d.kappa_h, d.r_g = float(inst.D_max), float(inst.kappa_h), float(inst.r_g)
     return d
+
+
+class _AuxState:
+    """A step-internals buffer and the number of FULL rollouts that have
+    written it (shared by the simulators that use the same buffer)."""
+    shared = {}     # buffer address -> state
+
+    def __init__(self, buf):
+        self.buf = buf
+        self.gen = 0
 
 
 class Sim:
@@ -132,6 +143,9 @@ class Sim:
         if counters is not None:
             o.counters = ctypes.cast(c_void_p(counters.data_ptr()), POINTER(c_uint32))
         L.check(self.lib.cord_rollout(self._h, _ptr(s0), _ptr(u), _ptr(traj), _ptr(status), byref(o), _stream()))
+        st = getattr(self, "_aux_state", None)
+        if st is not None and store == L.STORE_FULL:
+            st.gen += 1      # the step internals now belong to this trajectory
         return traj
 
     def backward(self, u, traj, traj_bar=None, sT_bar=None, store: int = L.STORE_FULL, ckpt_every: int = 10,
@@ -180,12 +194,37 @@ class Sim:
                     raise ValueError(f"aux buffer must be a contiguous float32 tensor on {self.device} "
                                      f"with at least {self.info.aux_floats} elements")
                 self._aux = buffer
+                self._aux_state = _AuxState.shared.get(buffer.data_ptr()) or _AuxState(buffer)
             elif getattr(self, "_aux", None) is None:
                 self._aux = self._empty(max(self.info.aux_floats, 1))
+                self._aux_state = _AuxState(self._aux)
+            _AuxState.shared[self._aux.data_ptr()] = self._aux_state
             L.check(self.lib.cord_sim_set_aux(self._h, _ptr(self._aux)))
         else:
             L.check(self.lib.cord_sim_set_aux(self._h, None))
             self._aux = None
+            self._aux_state = None
+
+    def aux_generation(self):
+        """Count of FULL rollouts that have written the step internals in use
+        (None without a buffer)."""
+        st = getattr(self, "_aux_state", None)
+        return None if st is None else st.gen
+
+    @contextlib.contextmanager
+    def aux_if_current(self, gen):
+        """Inside the block the step internals are used only if no FULL
+        rollout has overwritten them since generation `gen`; otherwise the
+        calls inside solve each step again from the stored states."""
+        st = getattr(self, "_aux_state", None)
+        if st is None or gen == st.gen:
+            yield
+            return
+        L.check(self.lib.cord_sim_set_aux(self._h, None))
+        try:
+            yield
+        finally:
+            L.check(self.lib.cord_sim_set_aux(self._h, _ptr(self._aux)))
 
     @property
     def aux(self):

@@ -28,6 +28,9 @@ class CordRollout(torch.autograd.Function):
         ctx.ckpt_every = ckpt_every
         if mode == "full":
             traj = sim.rollout(s0c, uc, store=L.STORE_FULL)
+            # the step internals this rollout wrote serve its backward only
+            # while no later FULL rollout has overwritten them
+            ctx.aux_gen = sim.aux_generation()
             ctx.save_for_backward(uc, traj)
             return traj
         if mode != "final":
@@ -43,7 +46,8 @@ class CordRollout(torch.autograd.Function):
         sim = ctx.sim
         g = g.contiguous()
         if ctx.mode == "full":
-            s0_bar, u_bar = sim.backward(u, saved, traj_bar=g, store=L.STORE_FULL)
+            with sim.aux_if_current(ctx.aux_gen):
+                s0_bar, u_bar = sim.backward(u, saved, traj_bar=g, store=L.STORE_FULL)
         else:
             s0_bar, u_bar = sim.backward(u, saved, sT_bar=g, store=L.STORE_CKPT, ckpt_every=ctx.ckpt_every)
         return None, s0_bar, u_bar, None, None

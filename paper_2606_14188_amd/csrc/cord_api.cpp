@@ -83,12 +83,25 @@ hipError_t launch_linearize(int cfg_index, int topo, int nmax, bool penalty, con
         ad.kept = (ns && ns[0] == '1') ? nullptr : ks.get(ks.ctx, kf);
         ad.kept_tg = wg;
         hipError_t e = linearize_rope_direct(nmax, ad, nblk, tmax, st);
-        if (e != hipSuccess || !a.jvp_out) return e;
+        if (e != hipSuccess) return e;
+        if (a.redo) {
+            // steps whose band factors met a non-positive pivot (an
+            // indefinite dF/dq*, e.g. a compressed rope) are done again by
+            // the iterative kernel, whose solves fall back to MINRES; the
+            // other workgroups of this launch return at once
+            KArgs ar = a;
+            ar.jvp_k = 0; ar.jvp_ds = nullptr; ar.jvp_du = nullptr; ar.jvp_out = nullptr;
+            e = cfg[cfg_index].linearize(ar, nblk, tmax, st);
+            if (e != hipSuccess) return e;
+        }
+        if (!a.jvp_out) return hipSuccess;
         KArgs aj = a;
-        aj.A = nullptr; aj.Bm = nullptr;
+        aj.A = nullptr; aj.Bm = nullptr; aj.redo = nullptr;
         return cfg[cfg_index].linearize(aj, nblk, tmax, st);
     }
-    return cfg[cfg_index].linearize(a, nblk, tmax, st);
+    KArgs ai = a;
+    ai.redo = nullptr;
+    return cfg[cfg_index].linearize(ai, nblk, tmax, st);
 }
 
 int bucket_of(int topo, int n) {
@@ -135,6 +148,8 @@ struct cord_sim {
     int seg_K = 0;
     int64_t* seg_off = nullptr;
     int32_t* d_queues = nullptr;     // one work-queue counter per group
+    int32_t* d_redo = nullptr;       // per (instance, step) flags of the direct linearization
+    int64_t n_steps = 0;             // sum T
     std::vector<hipStream_t> streams;
     hipStream_t cap_stream = nullptr;   // graph capture (the caller's stream may be the null stream)
     hipEvent_t fork_ev = nullptr;
@@ -495,7 +510,7 @@ int cord_sim_create(const cord_instance_desc* inst, int32_t n_inst, cord_sim** o
     s->desc.assign(inst, inst + n_inst);
     s->h.resize(n_inst);
     s->group_of.assign(n_inst, -1);
-    int64_t so = 0, uo = 0, to = 0, tns = 0, ao = 0, bo = 0, xo = 0;
+    int64_t so = 0, uo = 0, to = 0, tns = 0, ao = 0, bo = 0, xo = 0, steps = 0;
     int max_n = 0, max_T = 0;
     std::map<std::pair<int, int>, int> class_group;
     for (int i = 0; i < n_inst; ++i) {
@@ -504,6 +519,12 @@ int cord_sim_create(const cord_instance_desc* inst, int32_t n_inst, cord_sim** o
         fill_instdev(d, I);
         I.s_off = so; I.u_off = uo; I.traj_off = to; I.tns_off = tns; I.A_off = ao; I.B_off = bo;
         I.aux_off = xo;
+        I.t_off = (int32_t)steps;
+        steps += I.T;
+        if (steps > INT32_MAX) {
+            delete s;
+            return fail(CORD_EUNSUPPORTED, "more than 2^31 - 1 steps in one batch");
+        }
         xo += (int64_t)kAuxFields * I.T * I.n;
         so += I.n_s;
         uo += (int64_t)I.T * I.n_u;
@@ -533,6 +554,7 @@ int cord_sim_create(const cord_instance_desc* inst, int32_t n_inst, cord_sim** o
     s->info.s_floats = so; s->info.u_floats = uo; s->info.traj_floats = to;
     s->info.A_floats = ao; s->info.B_floats = bo; s->info.aux_floats = xo;
     s->info.max_n = max_n; s->info.max_T = max_T;
+    s->n_steps = steps;
     auto cleanup = [&](int code, const std::string& what) {
         cord_sim_destroy(s);
         return fail(code, "%s", what.c_str());
@@ -567,6 +589,7 @@ int cord_sim_destroy(cord_sim* s) {
     if (s->seg_off) (void)hipFree(s->seg_off);
     if (s->kept) (void)hipFree(s->kept);
     if (s->d_queues) (void)hipFree(s->d_queues);
+    if (s->d_redo) (void)hipFree(s->d_redo);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     for (hipEvent_t ev : s->join_ev) (void)hipEventDestroy(ev);
@@ -704,6 +727,18 @@ int cord_linearize(cord_sim* s, const float* traj, const float* u, float* A, flo
     if (jvp) { a.jvp_k = jvp->k; a.jvp_ds = jvp->ds; a.jvp_du = jvp->du; a.jvp_out = jvp->out; }
     hipStream_t st = (hipStream_t)stream;
     if (inst_status) CORD_HIP(launch_fill_i32(inst_status, s->info.n_inst, 0, st));
+    if (A || Bm) {
+        // per-step flags of the direct rope linearization (allocated once;
+        // without them a failed band factorization is reported as NOT_PD)
+        if (!s->d_redo && hipMalloc(&s->d_redo, sizeof(int32_t) * (size_t)s->n_steps) != hipSuccess) {
+            s->d_redo = nullptr;
+            (void)hipGetLastError();
+        }
+        if (s->d_redo) {
+            CORD_HIP(launch_fill_i32(s->d_redo, s->n_steps, 0, st));
+            a.redo = s->d_redo;
+        }
+    }
     for (const Group& g : s->groups) {
         a.ids = g.d_ids;
         a.n_ids = (int)g.ids.size();

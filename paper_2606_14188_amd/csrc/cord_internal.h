@@ -19,7 +19,7 @@ constexpr int kMaxGrip = 4;
 struct alignas(16) InstDev {
     int32_t kind, nx, ny, n;
     int32_t T, n_grip, n_obs, n_s;
-    int32_t n_u, grip_mode, pad1, pad2;
+    int32_t n_u, grip_mode, t_off, pad2;   // t_off: sum T (per-step flag tables)
     int32_t grip_node[kMaxGrip];
     int32_t obs_type[kMaxObs];
     float obs[kMaxObs][8];          // sphere: cx cy cz r; box: cx cy cz hx hy hz rho
@@ -74,6 +74,9 @@ struct KArgs {
     int32_t aux_mode;          // 1: rollout writes them; 2: backward / linearize read them
     float* kept;               // direct rope linearization: scratch slots, or null
     int32_t kept_tg;           // workgroup slots per CU in that scratch table
+    int32_t* redo;             // per (instance, step) at t_off + t: the direct linearization sets 1 where a
+                               // band factor met a non-positive pivot; the iterative linearize kernel run
+                               // with this set does only those steps (null: every step)
 };
 
 }  // namespace cord

@@ -170,6 +170,7 @@ __global__ __launch_bounds__(NT) void linearize_kernel(KArgs a) {
     const InstDev& I = a.inst[id];
     const int t = blockIdx.y;
     if (t >= I.T) return;
+    if (a.redo && !a.redo[I.t_off + t]) return;   // only the steps the direct kernel flagged
     Solver<TOPO, NT, PPT, NOBS> S;
     S.init(I, lds);
     const int n = I.n, ns = I.n_s, nu = I.n_u;

@@ -438,7 +438,13 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
         // floats are the two wavefronts' sinks
         if (wv == 0) ok = band_cholesky(LC, LI, N, UR);
         else if (wv == 1) ok = band_cholesky(UW, UD, N, UR + 64);
-        if (!ok && (threadIdx.x & 63) == 0 && a.status) atomicMax(&a.status[id], kStNotPD);
+        // a non-positive pivot: dF/dq* (or K) is not positive definite here
+        // (e.g. a compressed rope); the step is done again by the iterative
+        // kernel when the caller keeps per-step flags, else reported
+        if (!ok && (threadIdx.x & 63) == 0) {
+            if (a.redo) a.redo[I.t_off + t] = 1;
+            else if (a.status) atomicMax(&a.status[id], kStNotPD);
+        }
     }
     __syncthreads();
     // row layout of U for the descending solve: UR[i][m-1] = U(i, i+m)

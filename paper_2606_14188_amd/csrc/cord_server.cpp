@@ -110,7 +110,7 @@ struct Req {
     hipEvent_t ev = nullptr;
     // device pointers
     InstDev* d_inst = nullptr;
-    int32_t *d_ids = nullptr, *d_status = nullptr, *d_best = nullptr, *d_simst = nullptr;
+    int32_t *d_ids = nullptr, *d_status = nullptr, *d_best = nullptr, *d_simst = nullptr, *d_redo = nullptr;
     float *d_s0 = nullptr, *d_u = nullptr, *d_traj = nullptr, *d_sT = nullptr, *d_s0b = nullptr, *d_ub = nullptr;
     float *d_cost = nullptr, *d_bcost = nullptr, *d_ubest = nullptr, *d_tbest = nullptr, *d_A = nullptr, *d_B = nullptr;
     float* d_aux = nullptr;   // step internals of the candidates' rollouts
@@ -130,7 +130,7 @@ size_t footprint_of(int C, int T, int n, int ns, int nu, bool ab) {
     f += al(4ull * C * (T + 1) * ns);               // trajectories
     f += al(4ull * C);                              // costs
     f += al(4ull * T * nu) + al(4ull * (T + 1) * ns);
-    if (ab) f += al(4ull * T * ns * ns) + al(4ull * T * ns * nu);
+    if (ab) f += al(4ull * T * ns * ns) + al(4ull * T * ns * nu) + al(4ull * T);   // + per-step redo flags
     return f;
 }
 
@@ -270,10 +270,11 @@ bool carve_all(cord_server* s, Req* q) {
     if (ab) {
         q->d_A = carve<float>(s, q, 4ull * T * ns * ns);
         q->d_B = carve<float>(s, q, 4ull * T * ns * nu);
+        q->d_redo = carve<int32_t>(s, q, 4ull * T);
     }
     if (!q->d_inst || !q->d_ids || !q->d_status || !q->d_best || !q->d_simst || !q->d_s0 || !q->d_sT ||
         !q->d_s0b || !q->d_u || !q->d_ub || !q->d_traj || !q->d_cost || !q->d_bcost || !q->d_ubest ||
-        !q->d_tbest || !q->d_aux || (ab && (!q->d_A || !q->d_B))) {
+        !q->d_tbest || !q->d_aux || (ab && (!q->d_A || !q->d_B || !q->d_redo))) {
         for (auto& b : q->blocks) s->arena.release(b.first, b.second);
         q->blocks.clear();
         return false;
@@ -305,6 +306,7 @@ bool enqueue(cord_server* s, Req* q) {
         inst[c].A_off = 0;
         inst[c].B_off = 0;
         inst[c].aux_off = (int64_t)c * T * q->n * kAuxFields;
+        inst[c].t_off = 0;   // only the winner is linearized: its steps index the redo flags
     }
     int32_t* ids = reinterpret_cast<int32_t*>(sg.up + U.ids);
     for (int c = 0; c < C; ++c) ids[c] = c;
@@ -374,6 +376,8 @@ bool enqueue(cord_server* s, Req* q) {
         l.lin_zero_off = 1;
         l.status = nullptr;
         l.aux = q->d_aux; l.aux_mode = 2;
+        l.redo = q->d_redo;
+        SRV_HIP(launch_fill_i32(q->d_redo, T, 0, st));
         const int topo = q->r.inst.kind == CORD_ROPE ? kRope : kCloth;
         // one instance: the direct kernel keeps its vectors inside A (no scratch)
         SRV_HIP(launch_linearize(q->cfg, topo, bucket_of(topo, q->n), q->r.inst.grip_mode == CORD_GRIP_PENALTY, l, 1,

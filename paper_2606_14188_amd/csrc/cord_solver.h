@@ -36,6 +36,7 @@ constexpr int kNewtonMax = 40;
 constexpr int kLineSearchMax = 30;
 constexpr int kIpmMax = 60;
 constexpr int kPcgMax = 300;
+constexpr int kMinresMax = 600;
 constexpr float kPcgTolInner = 1e-3f;   // relative residual (preconditioned norm), Newton / IPM
 constexpr float kPcgTolAdj = 1e-6f;     // adjoint / tangent solves
 constexpr float kTolForce = 1e-5f;      // x force scale (m|g| + 1e-3 m/dt^2 h)
@@ -669,6 +670,100 @@ struct Solver {
         return ok;
     }
 
+    // Minimum residual method (Paige and Saunders, 1975) on the free DoFs:
+    // the solver of the derivative and interior-point systems once the
+    // conjugate gradient has met non-positive curvature.  Compression makes
+    // the exact dF/dq* indefinite at a stationary point of Psi that is not
+    // a minimum (a straight compressed rope); the implicit derivative of
+    // eq. (diff-sim) still exists there and this solves for it.  No
+    // preconditioner: the block-Jacobi blocks need not be positive definite
+    // then.  Lanczos vectors r1 (previous) and r2 (current, unnormalised),
+    // the two last search directions wa, wb and the iterate stay in
+    // registers.  Returns false if |b - A x| <= rtol |b| was not reached.
+    template <bool CONTACT>
+    __device__ __forceinline__ bool minres(const float b[PPT][3], float xs[PPT][3], float rtol) {
+        float r1[PPT][3], r2[PPT][3], y[PPT][3], wa[PPT][3], wb[PPT][3];
+        float bb = 0.f;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                xs[k][c] = 0.f;
+                r1[k][c] = isfree(k) ? b[k][c] : 0.f;
+                r2[k][c] = r1[k][c];
+                wa[k][c] = 0.f;
+                wb[k][c] = 0.f;
+                bb += r1[k][c] * r1[k][c];
+            }
+        const float beta1 = sqrtf(bsum(bb));
+        if (!(beta1 > 0.f)) return beta1 == 0.f;
+        float oldb = 0.f, beta = beta1, dbar = 0.f, epsln = 0.f, phibar = beta1, cs = -1.f, sn = 0.f;
+        for (int it = 0; it < kMinresMax; ++it) {
+            const float sc = 1.0f / beta;              // v = sc r2
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) y[k][c] = sc * r2[k][c];
+            publish(V, y, false, false);
+            apply<CONTACT>(y);
+            ++cnt[1];
+            float vy = 0.f;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (it > 0) y[k][c] -= (beta / oldb) * r1[k][c];
+                    vy += sc * r2[k][c] * y[k][c];
+                }
+            const float alfa = bsum(vy);
+            float yy = 0.f;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    y[k][c] -= (alfa / beta) * r2[k][c];
+                    yy += y[k][c] * y[k][c];
+                }
+            oldb = beta;
+            beta = sqrtf(bsum(yy));
+            const float oldeps = epsln;
+            const float delta = cs * dbar + sn * alfa;
+            const float gbar = sn * dbar - cs * alfa;
+            epsln = sn * beta;
+            dbar = -cs * beta;
+            const float gam = fmaxf(sqrtf(gbar * gbar + beta * beta), 1e-30f);
+            cs = gbar / gam;
+            sn = beta / gam;
+            const float phi = cs * phibar;
+            phibar = sn * phibar;
+            const float ig = 1.0f / gam;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    // new direction from v (= sc r2, before r2 moves on)
+                    const float wn = (sc * r2[k][c] - oldeps * wb[k][c] - delta * wa[k][c]) * ig;
+                    wb[k][c] = wa[k][c];
+                    wa[k][c] = wn;
+                    xs[k][c] += phi * wn;
+                    r1[k][c] = r2[k][c];
+                    r2[k][c] = y[k][c];
+                }
+            if (!(phibar > rtol * beta1)) return phibar == phibar;
+            if (!(beta > 0.f)) break;
+        }
+        return false;
+    }
+
+    // A derivative or interior-point solve: conjugate gradients, and the
+    // minimum residual method on the same system if non-positive curvature
+    // was met.  Flags NOT_PD only if that fails too.
+    template <bool CONTACT>
+    __device__ __forceinline__ void solve(const float b[PPT][3], float xs[PPT][3], float rtol) {
+        if (pcg<CONTACT>(b, xs, rtol)) return;
+        if (!minres<CONTACT>(b, xs, rtol)) status = max(status, kStNotPD);
+    }
+
     // Psi(y + DL) - Psi(y) with DL mirrored in LDS, in cancellation-free form
     // (each spring counted half at each end, each bending triplet at its
     // centre, inertia and gravity at free particles).
@@ -969,7 +1064,7 @@ struct Solver {
                     }
             }
             build_precond<true>();
-            pcg<true>(rhs, dD, kPcgTolInner);
+            solve<true>(rhs, dD, kPcgTolInner);
             ++cnt[2];
             float amax = 1.f / 0.995f;
             float dg[PPT][NOBS], dlm[PPT][NOBS];
@@ -997,6 +1092,174 @@ struct Solver {
             }
         }
         if (!conv) status = max(status, kStQP);
+        else if (hard) hard_polish();
+    }
+
+    // Hard contact: the interior point ends with a small positive lam * gap
+    // on every pair.  Fix its active set {lam_c > pi_c gap_c} (pi_c =
+    // n_c^T P_pp n_c) and solve min 1/2 D^T P D s.t. phi_c + n_c . D_p = 0
+    // over it, so the complementarity of eq. (dynamics-second-stage) holds
+    // exactly instead of to the interior point's floor.  Per particle the
+    // active normals (one or two) give a shift s_p onto the constraints and
+    // the projector Pi_p onto the complement of their span; the rest solves
+    // Pi P Pi w = -Pi P (D + s) by projected conjugate gradients
+    // (preconditioner Pi M^-1 Pi from the diagonal blocks of P).  The
+    // multipliers follow from (P D)_p = sum_c lam_c n_c.  The interior
+    // point's correction is kept if some particle has more than two active
+    // pairs or two nearly parallel ones, or if the result has a negative
+    // active multiplier or a penetrating inactive pair.
+    __device__ __forceinline__ void hard_polish() {
+        float pj[PPT][6], dn[PPT][3], n1[PPT][3], n2[PPT][3];
+        int na[PPT];
+        float c12[PPT];
+        float bad = 0.f;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            na[k] = 0;
+            c12[k] = 0.f;
+            float g1 = 0.f, g2 = 0.f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { n1[k][c] = 0.f; n2[k][c] = 0.f; }
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) {
+                if (!(o < nobs && isfree(k))) continue;
+                float t[3];
+                sym_mul(Bd[k], cn[k][o], t);
+                const float pi = dot3(cn[k][o], t);
+                if (!(clam[k][o] > pi * cgap[k][o])) continue;
+                const float gnow = cphi[k][o] + dot3(cn[k][o], dl[k]);
+                if (na[k] == 0) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) n1[k][c] = cn[k][o][c];
+                    g1 = gnow;
+                } else if (na[k] == 1) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) n2[k][c] = cn[k][o][c];
+                    g2 = gnow;
+                }
+                ++na[k];
+            }
+            float sh[3] = {0.f, 0.f, 0.f};
+            pj[k][0] = 1.f; pj[k][1] = 0.f; pj[k][2] = 0.f; pj[k][3] = 1.f; pj[k][4] = 0.f; pj[k][5] = 1.f;
+            if (!isfree(k)) {
+#pragma unroll
+                for (int i = 0; i < 6; ++i) pj[k][i] = 0.f;
+            } else if (na[k] == 1) {
+                sym_add_outer(pj[k], -1.f, n1[k]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sh[c] = -g1 * n1[k][c];
+            } else if (na[k] == 2) {
+                const float cc = dot3(n1[k], n2[k]);
+                const float det = 1.f - cc * cc;
+                if (!(det > 1e-4f)) bad = 1.f;
+                const float id = det > 1e-4f ? 1.0f / det : 0.f;
+                const float a1 = (-g1 + cc * g2) * id, a2 = (-g2 + cc * g1) * id;
+                float tx[3] = {n1[k][1] * n2[k][2] - n1[k][2] * n2[k][1], n1[k][2] * n2[k][0] - n1[k][0] * n2[k][2],
+                               n1[k][0] * n2[k][1] - n1[k][1] * n2[k][0]};
+                const float tl = sqrtf(dot3(tx, tx));
+                const float it = tl > 0.f ? 1.0f / tl : 0.f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { tx[c] *= it; sh[c] = a1 * n1[k][c] + a2 * n2[k][c]; }
+#pragma unroll
+                for (int i = 0; i < 6; ++i) pj[k][i] = 0.f;
+                sym_add_outer(pj[k], 1.f, tx);
+                c12[k] = cc;
+            } else if (na[k] > 2) {
+                bad = 1.f;
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dn[k][c] = isfree(k) ? dl[k][c] + sh[c] : 0.f;
+        }
+        if (bmax(bad) > 0.f) return;
+        build_precond<false>();
+        // residual of the projected stationarity: r = -Pi P dn
+        float r[PPT][3], z[PPT][3], pp[PPT][3], q[PPT][3], w[PPT][3], t3[3];
+        publish(V, dn);
+        apply<false>(q);
+        float rz = 0.f;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            sym_mul(pj[k], q[k], t3);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { r[k][c] = -t3[c]; w[k][c] = 0.f; }
+            sym_mul(Mi[k], r[k], t3);
+            sym_mul(pj[k], t3, z[k]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pp[k][c] = z[k][c];
+            rz += dot3(r[k], z[k]);
+        }
+        rz = bsum(rz);
+        const float rz0 = rz;
+        if (rz0 > 0.f) {
+            for (int it = 0; it < kPcgMax; ++it) {
+                publish(V, pp, false, false);
+                apply<false>(q);
+                float pq = 0.f;
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    sym_mul(pj[k], q[k], t3);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) q[k][c] = t3[c];
+                    pq += dot3(pp[k], q[k]);
+                }
+                pq = bsum(pq);
+                ++cnt[1];
+                if (!(pq > 0.f)) return;
+                const float alpha = rz / pq;
+                float rzn = 0.f;
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { w[k][c] += alpha * pp[k][c]; r[k][c] -= alpha * q[k][c]; }
+                    sym_mul(Mi[k], r[k], t3);
+                    sym_mul(pj[k], t3, z[k]);
+                    rzn += dot3(r[k], z[k]);
+                }
+                rzn = bsum(rzn);
+                if (!(rzn > kPcgTolAdj * kPcgTolAdj * rz0)) break;
+                const float beta = rzn / rz;
+                rz = rzn;
+#pragma unroll
+                for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) pp[k][c] = z[k][c] + beta * pp[k][c];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dn[k][c] += w[k][c];
+        // multipliers of the active pairs and the gaps of the others
+        publish(V, dn);
+        apply<false>(q);
+        const float ltol = -1e-5f * fscale;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (!isfree(k)) continue;
+            const float a1 = dot3(n1[k], q[k]), a2 = dot3(n2[k], q[k]);
+            float l1 = a1, l2 = 0.f;
+            if (na[k] == 2) {
+                const float cc = c12[k], id = 1.0f / (1.f - cc * cc);
+                l1 = (a1 - cc * a2) * id;
+                l2 = (a2 - cc * a1) * id;
+            }
+            if (na[k] >= 1 && !(l1 >= ltol)) bad = 1.f;
+            if (na[k] == 2 && !(l2 >= ltol)) bad = 1.f;
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) {
+                if (!(o < nobs)) continue;
+                float t[3];
+                sym_mul(Bd[k], cn[k][o], t);
+                if (clam[k][o] > dot3(cn[k][o], t) * cgap[k][o]) continue;
+                const float gp = cphi[k][o] + dot3(cn[k][o], dn[k]);
+                if (!(gp >= -10.f * kTolGap * (h + fabsf(cphi[k][o])))) bad = 1.f;
+            }
+        }
+        if (bmax(bad) > 0.f) return;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dl[k][c] = dn[k][c];
     }
 
     // -------------------------------------------------- step internals
@@ -1144,7 +1407,7 @@ struct Solver {
             }
         // stage 2: z = K^{-1} qb, K = P + N^T Lam N
         build_precond<true>();
-        if (!pcg<true>(qb, z, kPcgTolAdj)) status = max(status, kStNotPD);
+        solve<true>(qb, z, kPcgTolAdj);
         // e1 = (C - W - R^T - N^T Lam N) z ; gripped rows: bb -= (W z)_g
         publish(V, z);
         apply_third(t2, true);
@@ -1183,7 +1446,7 @@ struct Solver {
 #pragma unroll
             for (int c = 0; c < 3; ++c) rhs[k][c] = isfree(k) ? mdt2 * e1[k][c] - t1[k][c] : 0.f;
         build_precond<false>();
-        if (!pcg<false>(rhs, del, kPcgTolAdj)) status = max(status, kStNotPD);
+        solve<false>(rhs, del, kPcgTolAdj);
         const float imdt2 = 1.0f / mdt2;
 #pragma unroll
         for (int k = 0; k < PPT; ++k)
@@ -1283,7 +1546,7 @@ struct Solver {
                 r1[k][c] -= pdk[k] * ((x[k][c] - G[3 + c]) + d[k][c]) - G[6] * (G[13 + c] + dt * du[k][c]);
         }
         build_precond<false>();
-        if (!pcg<false>(r1, eps, kPcgTolAdj)) status = max(status, kStNotPD);
+        solve<false>(r1, eps, kPcgTolAdj);
 #pragma unroll
         for (int k = 0; k < PPT; ++k)
 #pragma unroll
@@ -1321,7 +1584,7 @@ struct Solver {
                 for (int c = 0; c < 3; ++c) r2[k][c] -= pdk[k] * dl[k][c];
         float eta[PPT][3];
         build_precond<true>();
-        if (!pcg<true>(r2, eta, kPcgTolAdj)) status = max(status, kStNotPD);
+        solve<true>(r2, eta, kPcgTolAdj);
 #pragma unroll
         for (int k = 0; k < PPT; ++k)
 #pragma unroll

@@ -8,7 +8,7 @@ import pytest
 
 import workloads as W
 from oracle.step import rollout as orollout
-from tests.parity import STATE_TOL, state_errors
+from tests.parity import GRAD_TOL, STATE_TOL, check, gradient_block_errors, state_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -110,14 +110,29 @@ def test_c4_mixed_batch_graph():
     print("classes", sim.classes(), "status", np.bincount(stc, minlength=5))
     assert (stc == 0).all()
     parts = sim.split(tr, "traj")
-    small = sorted(range(len(insts)), key=lambda i: insts[i].n * insts[i].T)
-    picks = [i for i in small if insts[i].kind == "rope"][::700][:2] + \
-            [i for i in small if insts[i].kind == "cloth"][::700][:2]
+    s0p, up = sim.split(b[0], "s"), sim.split(b[1], "u")
+    cots = sim.split(sT, "s")
+    order = sorted(range(len(insts)), key=lambda i: insts[i].n * insts[i].T)
+    ropes = [i for i in order if insts[i].kind == "rope"]
+    cloths = [i for i in order if insts[i].kind == "cloth"]
+    # across the n T range: the smallest, a middle one and the largest rope
+    # (256 nodes, 119 steps); the smallest and a middle cloth and the
+    # largest cloth the oracle finishes in about a minute (47 x 47 nodes
+    # over 34 steps; a 48 x 48 cloth over 60 or more steps would take it
+    # several minutes)
+    big = max((i for i in cloths if insts[i].T <= 35), key=lambda i: insts[i].n)
+    picks = [ropes[0], ropes[len(ropes) // 2], ropes[-1], cloths[0], cloths[len(cloths) // 2], big]
     for i in picks:
-        ref, _ = orollout(insts[i])
-        ex, ev = state_errors(parts[i], ref, insts[i].n)
-        print(f"C4 instance {i} {insts[i].kind} n={insts[i].n} T={insts[i].T}: x {ex:.2e} v {ev:.2e}")
+        print(f"C4 instance {i} {insts[i].kind} n={insts[i].n} T={insts[i].T}", flush=True)
+    from tests.oracle_pool import references
+    refs = references([insts[i] for i in picks], [cots[i] for i in picks])
+    for i, (ref, rst, s0r, ur) in zip(picks, refs):
+        inst = insts[i]
+        assert rst.max() == 0
+        ex, ev = state_errors(parts[i], ref, inst.n)
+        print(f"C4 instance {i}: x {ex:.2e} v {ev:.2e}", flush=True)
         assert ex <= STATE_TOL and ev <= STATE_TOL
+        check(gradient_block_errors(s0p[i], up[i], s0r, ur, inst.n), GRAD_TOL, f"C4 instance {i} gradient")
     j = picks[0]
     alone = Sim([insts[j]])
     ta = alone.rollout(alone.pack_states([insts[j].s0]), alone.pack_controls([insts[j].u]))

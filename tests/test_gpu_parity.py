@@ -273,6 +273,41 @@ def test_autograd_function():
     assert torch.equal(s0.grad, s0b2) and torch.equal(u.grad, ub2)
 
 
+def test_autograd_two_graphs_before_backward():
+    """With step internals kept, two differentiable rollouts are built before
+    the first one's backward runs: the second rollout has overwritten the
+    internals, so that backward solves its steps again and gives bitwise the
+    gradient of a simulator without step internals (and the second graph's
+    backward still uses the internals it owns)."""
+    import torch
+    from paper_2606_14188_amd import Sim, rollout
+    insts = W.small_rope_batch(3, 32, 10, seed=475)
+    sim = Sim(insts)
+    sim.use_aux(True)
+    plain = Sim(insts)
+    s0 = sim.pack_states([i.s0 for i in insts])
+    u1 = sim.pack_controls([i.u for i in insts]).requires_grad_(True)
+    u2 = (u1.detach() * 1.5).requires_grad_(True)
+    tr1 = rollout(sim, s0, u1, mode="full")
+    tr2 = rollout(sim, s0, u2, mode="full")
+    w = torch.randn_like(tr1)
+    (tr1 * w).sum().backward()
+    (tr2 * w).sum().backward()
+    r1 = plain.backward(u1.detach(), tr1.detach(), traj_bar=w)
+    r2 = plain.backward(u2.detach(), tr2.detach(), traj_bar=w)
+    torch.cuda.synchronize()
+    assert torch.equal(u1.grad, r1[1]) and torch.equal(u2.grad, r2[1])
+    # the first gradient against the oracle
+    tp, gp = sim.split(tr1.detach(), "traj"), sim.split(u1.grad, "u")
+    wp = sim.split(w, "traj")
+    for j in (0, 2):
+        inst = insts[j]
+        tr = tp[j].reshape(inst.T + 1, inst.n_s).astype(np.float64)
+        _, ur = rollout_backward(inst.replace(u=sim.split(u1.detach(), "u")[j].reshape(inst.T, -1).astype(np.float64)),
+                                 tr, traj_bar=wp[j].reshape(inst.T + 1, inst.n_s).astype(np.float64))
+        check({"u_bar": float(np.linalg.norm(gp[j] - ur.ravel()) / np.linalg.norm(ur))}, GRAD_TOL, f"graph 1 rope {j}")
+
+
 def _c2_bench_sim():
     """The full-size rope batch as the benchmark runs it: step internals
     kept by the rollout for the adjoint and the linearization."""

@@ -151,18 +151,7 @@ def test_hanging_cloth_detects_a_dropped_spring():
 
 
 # ---------------------------------------------------------------- P14 compression guard
-def compressed_rope(n=10, ratio=0.75, T=6, k=800.0, k_bend=5.0):
-    """A vertical rope (along z, gravity along its axis) held at both ends,
-    its nodes spaced ratio * l0; the top gripper pushes down along the
-    axis.  No obstacles: the configuration stays exactly straight."""
-    l0 = 0.04
-    z = 0.05 + ratio * l0 * np.arange(n)
-    pos = np.stack([np.zeros(n), np.zeros(n), z], axis=1)
-    s0 = np.concatenate([pos.ravel(), np.zeros(3 * n)])
-    u = np.zeros((T, 6))
-    u[:, 5] = -0.02
-    return W.rope(n, k=k, k_bend=k_bend, mass=0.01, dt=0.005, gamma=0.02, T=T, grip_nodes=(0, n - 1),
-                  ground=False, h=l0, s0=s0, u=u)
+compressed_rope = W.compressed_rope
 
 
 def test_p14_root_is_a_straight_saddle():

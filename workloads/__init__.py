@@ -19,4 +19,5 @@ from .gen import (  # noqa: F401
     random_cotangent,
     serve_trace,
     penalty_grasp,
+    compressed_rope,
 )

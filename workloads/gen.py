@@ -269,6 +269,23 @@ def config_c4(B: int = 4096, seed: int = 1004, max_cloth_side: int = 48, T_range
     return out
 
 
+def compressed_rope(n: int = 10, ratio: float = 0.75, T: int = 6, k: float = 800.0, k_bend: float = 5.0,
+                    push: float = 0.02) -> Instance:
+    """A vertical rope (along z, so gravity acts along its axis) held at both
+    ends by grippers, its nodes spaced ``ratio`` times the rest length
+    l0 = 4 cm; the top gripper pushes down along the axis at ``push`` m/s.
+    No obstacles: the rope stays exactly straight while compressed (the
+    compression-guard case)."""
+    l0 = 0.04
+    z = 0.05 + ratio * l0 * np.arange(n)
+    pos = np.stack([np.zeros(n), np.zeros(n), z], axis=1)
+    s0 = np.concatenate([pos.ravel(), np.zeros(3 * n)])
+    u = np.zeros((T, 6))
+    u[:, 5] = -push
+    return rope(n, k=k, k_bend=k_bend, mass=0.01, dt=0.005, gamma=0.02, T=T, grip_nodes=(0, n - 1),
+                ground=False, h=l0, s0=s0, u=u)
+
+
 def small_rope_batch(B: int, n: int, T: int, seed: int):
     """C2-style ropes at a smaller size (parity tests)."""
     return [_c2_instance(rng, n, T) for rng in _streams(seed, B)]
