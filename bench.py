@@ -67,27 +67,65 @@ def _oracle_job(args):
 
 def _one_thread():
     # one BLAS / OpenMP thread per worker process, so that `cores` is the
-    # number of threads the baseline used (set before numpy is imported)
+    # number of threads the baseline used (set before numpy is imported);
+    # the oracle and its libraries are imported before the clock starts
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         os.environ[k] = "1"
+    import numpy  # noqa: F401
+    import scipy.sparse.linalg  # noqa: F401
+    import oracle.derivatives  # noqa: F401
+    import workloads  # noqa: F401
 
 
-def cpu_baseline(workers: int, per_worker: int, T: int, with_lin: bool):
-    """The FP64 oracle on a bounded sample of the same workload: `workers`
-    processes, each running `per_worker` instances (forward, adjoint and
-    dense linearization, as in the GPU step) over the first T steps."""
+def _ready(_):
+    return os.getpid()
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_cores():
+    """Host cores this process may use, at most 16 (the machine's CPU share for one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(workers: int, sample: int, T: int, with_lin: bool):
+    """The FP64 oracle on a bounded sample of the same workload: `sample`
+    seeded instances of the rope batch (forward, adjoint and dense
+    linearization, as in the GPU step, over the first T steps) spread over
+    `workers` single-threaded processes, timed once the processes are up;
+    then one instance alone (the single-thread figure)."""
     import concurrent.futures as cf
     import multiprocessing as mp
-    jobs = [(i, 1024, 64, T, with_lin) for i in range(workers * per_worker)]
-    t0 = time.perf_counter()
+    jobs = [(i, 1024, 64, T, with_lin) for i in range(sample)]
     with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"),
                                 initializer=_one_thread) as ex:
+        list(ex.map(_ready, range(4 * workers)))          # every worker started and imported
+        t0 = time.perf_counter()
         res = list(ex.map(_oracle_job, jobs))
-    wall = time.perf_counter() - t0
+        wall = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        one = ex.submit(_oracle_job, jobs[0]).result()
+        wall1 = time.perf_counter() - t1
     ps = sum(r[1] for r in res)
+    what = f"forward + adjoint{' + dense A/B' if with_lin else ''} over {T} of 100 steps"
     return {"value": ps / wall, "unit": "particle-steps/s", "cores": workers, "kind": "oracle",
-            "sample": f"{len(jobs)} of the 1024 ropes (64 nodes), {T} of 100 steps, forward + adjoint"
-                      f"{' + dense A/B' if with_lin else ''}, {workers} single-threaded processes, {wall:.1f} s wall"}
+            "sample": f"{len(jobs)} of the 1024 ropes (64 nodes), {what}, {workers} single-threaded processes, "
+                      f"{wall:.1f} s wall after start-up",
+            "cpu_model": _cpu_model(),
+            "single_thread": {"value": one[1] / wall1, "unit": "particle-steps/s",
+                              "sample": f"rope 0 alone, {what}, {wall1:.1f} s"}}
 
 
 # ---------------------------------------------------------------- other workloads
@@ -145,15 +183,15 @@ def bench_c3(args):
     for j, nm in enumerate(names):
         ms[nm] = float(np.mean([x[j].elapsed_time(x[j + 1]) for x in ev]))
     ps = B * n * T
-    print(json.dumps({"workload": "cloth-32x32 x 256, T=60: forward (ckpt 10) + checkpointed adjoint + 6 JVP tangents/step",
-                      "ms_per_step": tms, "particle_steps_per_s": ps / (tms / 1e3), "kernel_ms": ms,
-                      "fwd_bwd_particle_steps_per_s": ps / ((ms["rollout_ckpt"] + ms["backward_ckpt"]) / 1e3)}), flush=True)
+    return {"workload": "cloth-32x32 x 256, T=60: forward (ckpt 10) + checkpointed adjoint + 6 JVP tangents/step",
+            "steps": args.steps, "ms_per_step": tms, "particle_steps_per_s": ps / (tms / 1e3), "kernel_ms": ms,
+            "fwd_bwd_particle_steps_per_s": ps / ((ms["rollout_ckpt"] + ms["backward_ckpt"]) / 1e3)}
 
 
 def bench_c4(args):
-    """4096 mixed ropes/cloths (cloth side capped at 32), forward + adjoint,
-    as one hipGraph of persistent per-class launches vs one launch per
-    instance."""
+    """4096 mixed ropes (16..256 nodes) and cloths (8x8..48x48), T 30..120,
+    forward + adjoint, as one hipGraph of persistent per-class launches,
+    persistent, grouped, and one launch per instance (the plain launch)."""
     import numpy as np
     import torch
     import workloads as W
@@ -202,7 +240,8 @@ def bench_c4(args):
         tms = _time(step, 1, max(1, args.steps // 2))
         out[name] = {"ms_per_step": tms, "particle_steps_per_s": ps / (tms / 1e3)}
         print(name, out[name], file=sys.stderr, flush=True)
-    print(json.dumps(out), flush=True)
+    out["graph_vs_per_instance"] = out["per_instance"]["ms_per_step"] / out["graph"]["ms_per_step"]
+    return out
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -281,10 +320,11 @@ def bench_probe(args):
     print(json.dumps(out), flush=True)
 
 
-def _serve_once(trace, slots):
+def _serve_once(trace, slots, discard=0.0):
     """Replay a request trace against one server; latencies are measured from
     each request's scheduled arrival (so a slow submit counts against the
-    server) to the moment its result is ready."""
+    server) to the moment its result is ready.  Requests that arrive in the
+    first `discard` seconds are served but left out of the latency figures."""
     import threading
     import numpy as np
     from paper_2606_14188_amd.serve import Server
@@ -305,9 +345,10 @@ def _serve_once(trace, slots):
     th.start()
     th.join()
     lat, fails = [], 0
-    for t, lt in zip(tickets, late):
+    for (ta, *_), t, lt in zip(trace, tickets, late):
         r = srv.wait(t, 600000)
-        lat.append(lt + r.latency)
+        if ta >= discard:
+            lat.append(lt + r.latency)
         fails += int(r.status != 0 or r.sim_status != 0)
         srv.release(t)
     wall = time.perf_counter() - t_start
@@ -315,32 +356,46 @@ def _serve_once(trace, slots):
     srv.close()
     lat = np.array(lat) * 1e3
     return {"slots": slots, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_ms": float(lat.mean()), "throughput_req_s": len(trace) / wall, "wall_s": wall,
-            "drain_s": wall - trace[-1][0],
+            "mean_ms": float(lat.mean()), "measured_requests": int(len(lat)),
+            "throughput_req_s": len(trace) / wall, "wall_s": wall, "drain_s": wall - trace[-1][0],
             "peak_queue": st["peak_queue"], "failed_or_flagged": fails}
 
 
-def bench_c5(args, rates=(200.0, 15.0), quiet=False):
-    """Served planning stream: Poisson arrivals, each request 128 candidates
-    x T=30 x 10 gradient steps on a rope (48..128) or cloth (16x16..32x32),
-    plus A_t/B_t along the winner for ropes.  Continuous batching (8 slots)
-    vs one request at a time, on the same trace, at the offered rate and at
-    a rate below the batched server's capacity."""
+def bench_c5(args, quiet=False):
+    """Served planning stream: each request plans 128 candidates x T=30 x 10
+    gradient steps on a rope (48..128 nodes, plus A_t/B_t along the winner)
+    or a cloth (16x16..32x32).  Continuous batching (8 slots) against one
+    request at a time on the same inputs:
+      capacity  a burst of requests all arriving at once, drained by each
+                server: requests per second each sustains; the offered
+                200 req/s divided by it is the utilisation rho;
+      stable    Poisson arrivals at 80 % of the batched capacity for
+                `serve_seconds` (first 2 s discarded): p50 / p99 latency of
+                both servers (one at a time is unstable at that rate if its
+                capacity is lower, and then says so)."""
     import workloads as W
-    out = {"workload": "planning stream: Poisson arrivals, 128 candidates x T=30 x 10 gradient steps, "
+    out = {"workload": "planning stream: 128 candidates x T=30 x 10 gradient steps, "
                        "ropes 48..128 (+A_t/B_t) / cloths 16x16..32x32"}
-    for rate in rates:
-        duration = args.serve_seconds if rate >= 100 else max(4.0, 4 * args.serve_seconds)
-        trace = W.serve_trace(rate, duration)
-        res = {"offered_req_s": rate, "duration_s": duration, "requests": len(trace)}
-        for name, slots in (("batched", args.slots), ("plain", 1)):
-            res[name] = _serve_once(trace, slots)
-            if not quiet:
-                print(rate, name, res[name], file=sys.stderr, flush=True)
-        # backlog left when the last request arrives: about one request's
-        # latency if the server keeps up with the offered rate
-        res["batched_keeps_up"] = bool(res["batched"]["drain_s"] < 1.0)
-        out[f"rate_{rate:g}"] = res
+    burst = [(0.0, inst, gn, goal) for (_, inst, gn, goal) in W.serve_trace(200.0, 0.4, seed=1015)]
+    cap = {}
+    for name, slots in (("batched", args.slots), ("plain", 1)):
+        r = _serve_once(burst, slots)
+        cap[name] = r["throughput_req_s"]
+        if not quiet:
+            print("capacity", name, r, file=sys.stderr, flush=True)
+    out["capacity"] = {"requests": len(burst), "batched_req_s": cap["batched"], "plain_req_s": cap["plain"],
+                       "rho_at_200_req_s": {"batched": 200.0 / cap["batched"], "plain": 200.0 / cap["plain"]},
+                       "offered_load_note": "rho > 1: the 200 req/s stream exceeds what one GPU serves; "
+                                            "its queue grows without bound"}
+    rate = 0.8 * cap["batched"]
+    trace = W.serve_trace(rate, args.serve_seconds)
+    res = {"offered_req_s": rate, "duration_s": args.serve_seconds, "requests": len(trace), "discarded_s": 2.0}
+    for name, slots in (("batched", args.slots), ("plain", 1)):
+        res[name] = _serve_once(trace, slots, discard=2.0)
+        res[name]["keeps_up"] = bool(res[name]["drain_s"] < 2.0)
+        if not quiet:
+            print("stable", name, res[name], file=sys.stderr, flush=True)
+    out["stable"] = res
     return out
 
 
@@ -352,18 +407,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-linearize", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--cpu-workers", type=int, default=8)
-    ap.add_argument("--cpu-per-worker", type=int, default=1)
+    ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes (default: host cores, at most 16)")
+    ap.add_argument("--cpu-sample", type=int, default=32, help="oracle instances of the rope batch")
     ap.add_argument("--cpu-T", type=int, default=100)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "probe", "copy"])
     ap.add_argument("--autotune", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--serve-seconds", type=float, default=22.0,
+                    help="length of the Poisson trace of the serving leg (the first 2 s are discarded)")
     ap.add_argument("--slots", type=int, default=8, help="device slots of the batched planning server")
     ap.add_argument("--no-aux", action="store_true",
                     help="re-solve every step in the adjoint and linearize instead of keeping the step internals")
     ap.add_argument("--grasp", default="dirichlet", choices=["dirichlet", "penalty"],
                     help="grasp of the rope batch (penalty: holonomic penalty with smoothed activation)")
-    ap.add_argument("--no-serve", action="store_true", help="skip the short planning-stream leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the planning-stream leg")
+    ap.add_argument("--no-extras", action="store_true", help="skip the cloth (C3) and mixed-batch (C4) legs")
     ap.add_argument("--overlap", action="store_true",
                     help="run the adjoint and the linearization concurrently on two streams, both after "
                          "the rollout (default: one after the other on one stream, so that each kernel's "
@@ -375,9 +432,11 @@ def main():
         sys.exit(2)
 
     if args.workload == "c3":
-        return bench_c3(args)
+        print(json.dumps(bench_c3(args)), flush=True)
+        return
     if args.workload == "c4":
-        return bench_c4(args)
+        print(json.dumps(bench_c4(args)), flush=True)
+        return
     if args.workload == "copy":
         return copy_calibration()
     if args.workload == "probe":
@@ -390,7 +449,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         # before any GPU initialisation: the pool is started from a clean process
-        cpu = cpu_baseline(args.cpu_workers, args.cpu_per_worker, args.cpu_T, with_lin)
+        cpu = cpu_baseline(args.cpu_workers or cpu_cores(), args.cpu_sample, args.cpu_T, with_lin)
         print("cpu baseline:", json.dumps(cpu), file=sys.stderr, flush=True)
 
     import numpy as np
@@ -508,11 +567,26 @@ def main():
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = profiled_traffic(dom) if args.grasp == "dirichlet" else None
     roof["kernel"] = dom
-    serve = None
-    if not args.no_serve:
+    serve, extras = None, None
+    if with_lin:
         del A, Bm
-        torch.cuda.empty_cache()
-        serve = bench_c5(args, quiet=True)
+    del sim, sim_lin
+    torch.cuda.empty_cache()
+    # the other workloads: reported beside the headline figure (a failure
+    # there is recorded instead of losing the line)
+    if not args.no_extras:
+        extras = {}
+        for name, fn in (("c3", bench_c3), ("c4", bench_c4)):
+            try:
+                extras[name] = fn(args)
+            except Exception as e:      # noqa: BLE001
+                extras[name] = {"error": repr(e)}
+            torch.cuda.empty_cache()
+    if not args.no_serve:
+        try:
+            serve = bench_c5(args)
+        except Exception as e:          # noqa: BLE001
+            serve = {"error": repr(e)}
     out = {
         "metric": "particle-steps/s fwd+bwd (rope/cloth batch); MPC plan p50/p99 ms vs plain",
         "value": value,
@@ -538,6 +612,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "serve": serve,
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
 

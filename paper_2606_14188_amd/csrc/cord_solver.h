@@ -37,6 +37,7 @@ constexpr int kLineSearchMax = 30;
 constexpr int kIpmMax = 60;
 constexpr int kPcgMax = 300;
 constexpr int kMinresMax = 600;
+constexpr float kMinresAccept = 1e-4f;  // true relative residual accepted after the last MINRES pass
 constexpr float kPcgTolInner = 1e-3f;   // relative residual (preconditioned norm), Newton / IPM
 constexpr float kPcgTolAdj = 1e-6f;     // adjoint / tangent solves
 constexpr float kTolForce = 1e-5f;      // x force scale (m|g| + 1e-3 m/dt^2 h)
@@ -254,6 +255,7 @@ struct Solver {
 
     int status;
     uint32_t cnt[4];   // Newton its, PCG its, interior-point its, steps
+    float pcpd;        // 1 if every preconditioner block of this thread is positive definite
 
     __device__ __forceinline__ int pidx(int k) const { return (int)threadIdx.x + k * NT; }
     __device__ __forceinline__ bool active(int k) const { return grip[k] != -2; }
@@ -600,14 +602,27 @@ struct Solver {
         }
     }
 
-    // block-Jacobi preconditioner from Bd (+ contact weights)
+    // block-Jacobi preconditioner from Bd (+ contact weights); pcpd = 0 if
+    // the Hessian block Bd of some particle of this thread is not positive
+    // definite (Sylvester's criterion), which makes the preconditioned
+    // residual norm meaningless.  The test is taken before the contact
+    // weights are added: they only add positive semi-definite terms, and
+    // the minors of a block with a weight many orders above the mass term
+    // would be lost to cancellation.
     template <bool CONTACT>
     __device__ __forceinline__ void build_precond() {
+        pcpd = 1.f;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             float m[6];
 #pragma unroll
             for (int i = 0; i < 6; ++i) m[i] = Bd[k][i];
+            if (isfree(k)) {
+                const float m2 = m[0] * m[3] - m[1] * m[1];
+                const float m3 = m[0] * (m[3] * m[5] - m[4] * m[4]) - m[1] * (m[1] * m[5] - m[4] * m[2]) +
+                                 m[2] * (m[1] * m[4] - m[3] * m[2]);
+                if (!(m[0] > 0.f && m2 > 0.f && m3 > 0.f)) pcpd = 0.f;
+            }
             if constexpr (CONTACT) {
 #pragma unroll
                 for (int o = 0; o < NOBS; ++o)
@@ -671,15 +686,20 @@ struct Solver {
     }
 
     // Minimum residual method (Paige and Saunders, 1975) on the free DoFs:
-    // the solver of the derivative and interior-point systems once the
-    // conjugate gradient has met non-positive curvature.  Compression makes
-    // the exact dF/dq* indefinite at a stationary point of Psi that is not
-    // a minimum (a straight compressed rope); the implicit derivative of
-    // eq. (diff-sim) still exists there and this solves for it.  No
-    // preconditioner: the block-Jacobi blocks need not be positive definite
-    // then.  Lanczos vectors r1 (previous) and r2 (current, unnormalised),
-    // the two last search directions wa, wb and the iterate stay in
-    // registers.  Returns false if |b - A x| <= rtol |b| was not reached.
+    // the solver of the derivative and interior-point systems when conjugate
+    // gradients cannot be used.  Compression makes the exact dF/dq*
+    // indefinite at a stationary point of Psi that is not a minimum (a
+    // straight compressed rope); the implicit derivative of eq. (diff-sim)
+    // still exists there and this solves for it.  No preconditioner: the
+    // block-Jacobi blocks need not be positive definite then.  Lanczos
+    // vectors r1 (previous) and r2 (current, unnormalised), the two last
+    // search directions wa, wb and the iterate stay in registers.  Each pass
+    // runs until its recursive residual estimate is below rtol |b|; in FP32
+    // the Lanczos vectors lose orthogonality, so the true residual b - A x
+    // is then formed and the method restarts on it (iterative refinement,
+    // at most three passes).  The true residual cannot go below about
+    // eps cond(A) |b| (its own rounding), so the solve is accepted once it
+    // is within rtol |b| or, after the last pass, within kMinresAccept |b|.
     template <bool CONTACT>
     __device__ __forceinline__ bool minres(const float b[PPT][3], float xs[PPT][3], float rtol) {
         float r1[PPT][3], r2[PPT][3], y[PPT][3], wa[PPT][3], wb[PPT][3];
@@ -689,78 +709,96 @@ struct Solver {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 xs[k][c] = 0.f;
-                r1[k][c] = isfree(k) ? b[k][c] : 0.f;
-                r2[k][c] = r1[k][c];
-                wa[k][c] = 0.f;
-                wb[k][c] = 0.f;
-                bb += r1[k][c] * r1[k][c];
+                const float bk = isfree(k) ? b[k][c] : 0.f;
+                bb += bk * bk;
             }
-        const float beta1 = sqrtf(bsum(bb));
-        if (!(beta1 > 0.f)) return beta1 == 0.f;
-        float oldb = 0.f, beta = beta1, dbar = 0.f, epsln = 0.f, phibar = beta1, cs = -1.f, sn = 0.f;
-        for (int it = 0; it < kMinresMax; ++it) {
-            const float sc = 1.0f / beta;              // v = sc r2
-#pragma unroll
-            for (int k = 0; k < PPT; ++k)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) y[k][c] = sc * r2[k][c];
-            publish(V, y, false, false);
-            apply<CONTACT>(y);
-            ++cnt[1];
-            float vy = 0.f;
+        const float bnorm = sqrtf(bsum(bb));
+        if (!(bnorm > 0.f)) return bnorm == 0.f;
+        for (int pass = 0; pass <= 3; ++pass) {
+            // r1 = b - A xs
+            if (pass > 0) {
+                publish(V, xs, false, false);
+                apply<CONTACT>(y);
+            }
+            float rr = 0.f;
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    if (it > 0) y[k][c] -= (beta / oldb) * r1[k][c];
-                    vy += sc * r2[k][c] * y[k][c];
+                    r1[k][c] = isfree(k) ? b[k][c] - (pass > 0 ? y[k][c] : 0.f) : 0.f;
+                    r2[k][c] = r1[k][c];
+                    wa[k][c] = 0.f;
+                    wb[k][c] = 0.f;
+                    rr += r1[k][c] * r1[k][c];
                 }
-            const float alfa = bsum(vy);
-            float yy = 0.f;
+            const float beta1 = sqrtf(bsum(rr));
+            if (!(beta1 > rtol * bnorm)) return beta1 == beta1;
+            if (pass == 3) return beta1 <= kMinresAccept * bnorm;
+            float oldb = 0.f, beta = beta1, dbar = 0.f, epsln = 0.f, phibar = beta1, cs = -1.f, sn = 0.f;
+            for (int it = 0; it < kMinresMax; ++it) {
+                const float sc = 1.0f / beta;              // v = sc r2
 #pragma unroll
-            for (int k = 0; k < PPT; ++k)
+                for (int k = 0; k < PPT; ++k)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    y[k][c] -= (alfa / beta) * r2[k][c];
-                    yy += y[k][c] * y[k][c];
-                }
-            oldb = beta;
-            beta = sqrtf(bsum(yy));
-            const float oldeps = epsln;
-            const float delta = cs * dbar + sn * alfa;
-            const float gbar = sn * dbar - cs * alfa;
-            epsln = sn * beta;
-            dbar = -cs * beta;
-            const float gam = fmaxf(sqrtf(gbar * gbar + beta * beta), 1e-30f);
-            cs = gbar / gam;
-            sn = beta / gam;
-            const float phi = cs * phibar;
-            phibar = sn * phibar;
-            const float ig = 1.0f / gam;
+                    for (int c = 0; c < 3; ++c) y[k][c] = sc * r2[k][c];
+                publish(V, y, false, false);
+                apply<CONTACT>(y);
+                ++cnt[1];
+                float vy = 0.f;
 #pragma unroll
-            for (int k = 0; k < PPT; ++k)
+                for (int k = 0; k < PPT; ++k)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    // new direction from v (= sc r2, before r2 moves on)
-                    const float wn = (sc * r2[k][c] - oldeps * wb[k][c] - delta * wa[k][c]) * ig;
-                    wb[k][c] = wa[k][c];
-                    wa[k][c] = wn;
-                    xs[k][c] += phi * wn;
-                    r1[k][c] = r2[k][c];
-                    r2[k][c] = y[k][c];
-                }
-            if (!(phibar > rtol * beta1)) return phibar == phibar;
-            if (!(beta > 0.f)) break;
+                    for (int c = 0; c < 3; ++c) {
+                        if (it > 0) y[k][c] -= (beta / oldb) * r1[k][c];
+                        vy += sc * r2[k][c] * y[k][c];
+                    }
+                const float alfa = bsum(vy);
+                float yy = 0.f;
+#pragma unroll
+                for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        y[k][c] -= (alfa / beta) * r2[k][c];
+                        yy += y[k][c] * y[k][c];
+                    }
+                oldb = beta;
+                beta = sqrtf(bsum(yy));
+                const float oldeps = epsln;
+                const float delta = cs * dbar + sn * alfa;
+                const float gbar = sn * dbar - cs * alfa;
+                epsln = sn * beta;
+                dbar = -cs * beta;
+                const float gam = fmaxf(sqrtf(gbar * gbar + beta * beta), 1e-30f);
+                cs = gbar / gam;
+                sn = beta / gam;
+                const float phi = cs * phibar;
+                phibar = sn * phibar;
+                const float ig = 1.0f / gam;
+#pragma unroll
+                for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        // new direction from v (= sc r2, before r2 moves on)
+                        const float wn = (sc * r2[k][c] - oldeps * wb[k][c] - delta * wa[k][c]) * ig;
+                        wb[k][c] = wa[k][c];
+                        wa[k][c] = wn;
+                        xs[k][c] += phi * wn;
+                        r1[k][c] = r2[k][c];
+                        r2[k][c] = y[k][c];
+                    }
+                if (!(phibar > 0.5f * rtol * bnorm) || !(beta > 0.f)) break;
+            }
         }
         return false;
     }
 
-    // A derivative or interior-point solve: conjugate gradients, and the
-    // minimum residual method on the same system if non-positive curvature
-    // was met.  Flags NOT_PD only if that fails too.
+    // A derivative or interior-point solve: conjugate gradients, or MINRES if
+    // they meet non-positive curvature or if some preconditioner block is
+    // not positive definite (a compressed particle; the preconditioned
+    // residual norm is then no norm).  Flags NOT_PD only if MINRES fails.
     template <bool CONTACT>
     __device__ __forceinline__ void solve(const float b[PPT][3], float xs[PPT][3], float rtol) {
-        if (pcg<CONTACT>(b, xs, rtol)) return;
+        if (bmin(pcpd) > 0.f && pcg<CONTACT>(b, xs, rtol)) return;
         if (!minres<CONTACT>(b, xs, rtol)) status = max(status, kStNotPD);
     }
 
@@ -1172,6 +1210,7 @@ struct Solver {
         }
         if (bmax(bad) > 0.f) return;
         build_precond<false>();
+        if (!(bmin(pcpd) > 0.f)) return;   // P not positive definite: a nonconvex QP, keep the interior point
         // residual of the projected stationarity: r = -Pi P dn
         float r[PPT][3], z[PPT][3], pp[PPT][3], q[PPT][3], w[PPT][3], t3[3];
         publish(V, dn);
