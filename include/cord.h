@@ -290,6 +290,30 @@ int cord_rollout_backward(cord_sim* sim, const float* u, const float* traj,
                           const float* traj_bar, float* s0_bar, float* u_bar,
                           int32_t* inst_status, const cord_backward_opts* opts, void* stream);
 
+/*
+ * cord_rollout_backward without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * cord_rollout_backward, bitwise the same outputs, except:
+ *   - the checkpoint offsets and the workspace of the recomputed segments
+ *     (CORD_STORE_CKPT) live in a static device array of the library,
+ *     64 MiB on every GPU it runs on, held until the process ends; a call
+ *     needing more (8 n_inst bytes of table rounded up to a multiple of
+ *     256, plus 4 ckpt_every sum(n_s) bytes) returns CORD_ETOOBIG;
+ *   - the kernels are launched one per size class on `stream`, whatever
+ *     the simulator's launch mode (the persistent and graph modes would
+ *     create streams, queues and graphs);
+ *   - every call on one GPU shares that array: calls that overlap on one
+ *     GPU (other streams, other threads, other simulators) race and must be
+ *     ordered by the caller.
+ * No hipMalloc, hipFree or allocating library call is made.  CORD_EHIP if
+ * the device address of the array could not be obtained when the simulator
+ * was created.
+ */
+int cord_rollout_backward_noalloc(cord_sim* sim, const float* u, const float* traj,
+                                  const float* traj_bar, float* s0_bar, float* u_bar,
+                                  int32_t* inst_status, const cord_backward_opts* opts, void* stream);
+
 /* Tangents for cord_linearize's JVP mode: per step t, k tangent pairs
  * (ds_t, du_t) map to ds_{t+1} = A_t ds_t + B_t du_t (steps independent). */
 typedef struct {

@@ -149,6 +149,8 @@ struct cord_sim {
     int64_t* seg_off = nullptr;
     int32_t* d_queues = nullptr;     // one work-queue counter per group
     int32_t* d_redo = nullptr;       // per (instance, step) flags of the direct linearization
+    void* noalloc = nullptr;         // this device's static scratch (cord_rollout_backward_noalloc)
+    hipError_t noalloc_err = hipSuccess;
     int64_t n_steps = 0;             // sum T
     std::vector<hipStream_t> streams;
     hipStream_t cap_stream = nullptr;   // graph capture (the caller's stream may be the null stream)
@@ -507,6 +509,10 @@ int cord_sim_create(const cord_instance_desc* inst, int32_t n_inst, cord_sim** o
     if (!s) return fail(CORD_ENOMEM, "host allocation");
     if (hipGetDevice(&s->device) != hipSuccess) { delete s; return fail(CORD_EHIP, "hipGetDevice failed"); }
     if (hipDeviceGetAttribute(&s->n_cu, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess) s->n_cu = 1;
+    // the address of this device's copy of the no-alloc scratch, looked up
+    // here with the device current (an error is reported by the entry point)
+    s->noalloc_err = noalloc_scratch(s->device, &s->noalloc);
+    if (s->noalloc_err != hipSuccess) (void)hipGetLastError();
     s->desc.assign(inst, inst + n_inst);
     s->h.resize(n_inst);
     s->group_of.assign(n_inst, -1);
@@ -712,6 +718,57 @@ int cord_rollout_backward(cord_sim* s, const float* u, const float* traj, const 
     a.s0_bar = s0_bar; a.u_bar = u_bar; a.status = inst_status; a.counters = o.counters;
     if (s->aux && o.store == CORD_STORE_FULL) { a.aux = s->aux; a.aux_mode = 2; }
     return launch_all(s, kOpBackward, a, (hipStream_t)stream);
+}
+
+int cord_rollout_backward_noalloc(cord_sim* s, const float* u, const float* traj, const float* traj_bar,
+                                  float* s0_bar, float* u_bar, int32_t* inst_status, const cord_backward_opts* opts,
+                                  void* stream) {
+    g_err.clear();
+    if (!s || !traj || !s0_bar) return fail(CORD_EINVAL, "cord_rollout_backward_noalloc: NULL sim, traj or s0_bar");
+    if ((!u || !u_bar) && s->info.u_floats > 0)
+        return fail(CORD_EINVAL, "cord_rollout_backward_noalloc: NULL u or u_bar");
+    cord_backward_opts o{};
+    o.store = CORD_STORE_FULL;
+    if (opts) o = *opts;
+    if (o.store != CORD_STORE_FULL && o.store != CORD_STORE_CKPT)
+        return fail(CORD_EINVAL, "cord_rollout_backward_noalloc: store must be FULL or CKPT");
+    if (o.store == CORD_STORE_CKPT && o.ckpt_every < 1)
+        return fail(CORD_EINVAL, "cord_rollout_backward_noalloc: ckpt_every must be >= 1");
+    if (!s->noalloc)
+        return fail(CORD_EHIP, "cord_rollout_backward_noalloc: no device scratch (%s)", hipGetErrorString(s->noalloc_err));
+    hipStream_t st = (hipStream_t)stream;
+    KArgs a = base_args(s);
+    a.store = o.store;
+    a.ckpt_every = o.store == CORD_STORE_CKPT ? o.ckpt_every : 1;
+    a.use_kappa_bwd = o.use_kappa_bwd;
+    if (o.store == CORD_STORE_CKPT) {
+        const int B = (int)s->h.size();
+        const int64_t K = o.ckpt_every;
+        const size_t table = ((size_t)8 * B + 255) / 256 * 256;
+        const int64_t seg = K * s->info.s_floats;
+        if (seg > (int64_t)((kNoAllocScratchBytes - std::min(table, kNoAllocScratchBytes)) / sizeof(float)))
+            return fail(CORD_ETOOBIG, "cord_rollout_backward_noalloc: needs %zu + %lld bytes of scratch, the maximum is %zu",
+                        table, (long long)(4 * seg), kNoAllocScratchBytes);
+        int64_t* off = static_cast<int64_t*>(s->noalloc);
+        CORD_HIP(launch_ckpt_offsets(s->d_inst, B, o.ckpt_every, off, st));
+        a.ckpt_off = off;
+        a.seg = reinterpret_cast<float*>(static_cast<char*>(s->noalloc) + table);
+        a.seg_off = nullptr;   // K n_s floats per instance in instance order
+    }
+    a.u = u; a.traj_in = traj; a.traj_bar = traj_bar; a.sT_bar = o.sT_bar;
+    a.s0_bar = s0_bar; a.u_bar = u_bar; a.status = inst_status; a.counters = o.counters;
+    if (s->aux && o.store == CORD_STORE_FULL) { a.aux = s->aux; a.aux_mode = 2; }
+    // one launch per size class, whatever the simulator's launch mode (the
+    // persistent and graph modes create streams, queues and graphs)
+    int count = 0;
+    const KernelCfg* cfg = kernel_configs(&count);
+    for (const Group& G : s->groups) {
+        a.ids = G.d_ids;
+        a.n_ids = (int)G.ids.size();
+        a.queue = nullptr;
+        CORD_HIP(launch_op(cfg[G.cfg], kOpBackward, a, a.n_ids, st));
+    }
+    return CORD_OK;
 }
 
 int cord_linearize(cord_sim* s, const float* traj, const float* u, float* A, float* Bm, const cord_jvp* jvp,

@@ -31,4 +31,14 @@ const KernelCfg* kernel_configs(int* count);
 size_t linearize_rope_direct_scratch(int nmax, int* wg_per_cu);
 hipError_t linearize_rope_direct(int nmax, const KArgs& a, int nblk, int tmax, hipStream_t s);
 
+// Static device scratch of cord_rollout_backward_noalloc (64 MiB per GPU):
+// the checkpoint offset table (int64 per instance, padded to 256 bytes)
+// followed by the recomputed-segment workspace (K n_s floats per instance).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+// This GPU's address of that scratch (looked up once per device, with the
+// device current).
+hipError_t noalloc_scratch(int device, void** out);
+// out[b] = sum_{b' < b} (ceil(T/K) + 1) n_s over the instance table.
+hipError_t launch_ckpt_offsets(const InstDev* inst, int B, int K, int64_t* out, hipStream_t s);
+
 }  // namespace cord

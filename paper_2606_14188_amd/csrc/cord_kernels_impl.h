@@ -121,7 +121,9 @@ __global__ __launch_bounds__(NT) void backward_kernel(KArgs a) {
                 adjoint_step<TOPO, NT, PPT, NOBS>(S, a, I, t, xb, vb, ub);
             }
         } else {
-            float* ws = a.seg + a.seg_off[id];
+            // per-instance workspace: from the offset table, or K n_s floats
+            // per instance in instance order when there is none
+            float* ws = a.seg + (a.seg_off ? a.seg_off[id] : (int64_t)K * I.s_off);
             const int nseg = (T + K - 1) / K;
             for (int sg = nseg - 1; sg >= 0; --sg) {
                 const int t0 = sg * K, t1 = min(T, t0 + K);
