@@ -400,6 +400,44 @@ int cord_autotune(cord_sim* sim, const float* s0, const float* u, int32_t sample
 int cord_sim_classes(const cord_sim* sim, int32_t* topo, int32_t* nmax, int32_t* nt, int32_t* ppt,
                      int32_t* n_inst, int32_t cap, int32_t* count);
 
+/* ---------------------------------------------------------------- conformal calibration */
+/*
+ * Conformal calibration of the one-step model error (Sec. 4.4,
+ * "Calibrated Reachability Guarantees via Conformal Prediction").  A
+ * calibration set of n perceived-state transitions (q_i, u_i, q_i+) is a
+ * simulator of n instances with T = 1 (the geometry, material and
+ * obstacles of each pair; quasi-static gamma = 1 is the paper's model).
+ *
+ * cord_cp_scores: the nonconformity scores s_i = |q_i+ - f(q_i, u_i)|_2 over
+ * the node positions, f being one step of the simulator (at kappa_fwd).
+ *   s_bar   device [n_s] per instance: the perceived state (positions used;
+ *           the velocity block is the step's input velocity)
+ *   u       device [n_u] per instance
+ *   s_next  device [n_s] per instance: the perceived next state (only the
+ *           position block is read)
+ *   scores  device float[n_inst] (output)
+ * The library keeps a device buffer for the predictions (allocated on the
+ * first call).  Errors: CORD_EINVAL (NULL buffer, an instance with T != 1),
+ * CORD_ENOMEM, CORD_EHIP.
+ *
+ * cord_cp_radius: for a trajectory-level miscoverage delta over `horizon`
+ * steps, the radius r_CP = s_(k), the k-th smallest score with
+ * k = ceil((n + 1)(1 - delta / horizon)) evaluated in double precision
+ * with a margin of 1e-9 (so that a decimal delta whose exact product is an
+ * integer does not round k up), or +infinity if k > n.  Ties are ordered
+ * by index and a NaN score after every number.
+ *   scores  device float[n], 1 <= n <= 65536
+ *   radius  device float (output);  index  device int32 (output, may be
+ *           NULL): the calibration pair whose score is the radius, -1 for
+ *           +infinity
+ * Errors: CORD_EINVAL (NULL scores or radius, n < 1, horizon < 1,
+ * delta / horizon outside (0, 1)), CORD_EUNSUPPORTED (n > 65536), CORD_EHIP.
+ */
+int cord_cp_scores(cord_sim* sim, const float* s_bar, const float* u, const float* s_next, float* scores,
+                   int32_t* inst_status, void* stream);
+int cord_cp_radius(const float* scores, int32_t n, double delta, int32_t horizon, float* radius,
+                   int32_t* index, void* stream);
+
 /* ---------------------------------------------------------------- planning service */
 /*
  * Gradient-based trajectory planning (the nominal (z, v) of Sec. 4.2, stage

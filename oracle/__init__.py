@@ -22,6 +22,7 @@ sdf          signed distances, normals and curvatures of the obstacles
 step         one time step (stage 1 + stage 2) and rollouts
 derivatives  per-step JVP / VJP, dense A_t / B_t, rollout gradient
 planner      reference projected-gradient planner (cost, gradient, step, argmin)
+conformal    conformal radius of the one-step model error (scores, order statistic)
 """
 STATUS_OK = 0
 STATUS_NEWTON_NOCONV = 1

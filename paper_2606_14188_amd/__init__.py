@@ -7,13 +7,13 @@ torch's current stream) and `CordRollout` (torch.autograd.Function).
 """
 from ._lib import CordError, load  # noqa: F401
 
-__all__ = ["Sim", "CordRollout", "rollout", "load", "CordError"]
+__all__ = ["Sim", "CordRollout", "rollout", "cp_radius", "load", "CordError"]
 
 
 def __getattr__(name):
-    if name == "Sim":
-        from .api import Sim
-        return Sim
+    if name in ("Sim", "cp_radius"):
+        from . import api
+        return getattr(api, name)
     if name in ("CordRollout", "rollout"):
         from . import autograd
         return getattr(autograd, name)

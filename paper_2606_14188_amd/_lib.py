@@ -92,6 +92,8 @@ _EXPORTS = {
                                         c_void_p, POINTER(BackwardOpts), c_void_p]),
     "cord_rollout_backward_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                                 c_void_p, POINTER(BackwardOpts), c_void_p]),
+    "cord_cp_scores": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "cord_cp_radius": (c_int32, [c_void_p, c_int32, ctypes.c_double, c_int32, c_void_p, c_void_p, c_void_p]),
     "cord_linearize": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(Jvp),
                                  c_void_p, c_void_p]),
     "cord_abi_sizes": (c_int32, [POINTER(c_int64), c_int32]),

@@ -179,6 +179,15 @@ class Sim:
                                         _ptr(status), _stream()))
         return (A if dense else None), (Bm if want_B else None), out
 
+    # ------------------------------------------------------------ conformal calibration
+    def cp_scores(self, s_bar, u, s_next, status=None):
+        """Nonconformity scores |q+ - f(q, u)|_2 of a calibration set (one
+        instance of T = 1 per pair): a float32 tensor of B scores."""
+        scores = self._empty(self.B)
+        L.check(self.lib.cord_cp_scores(self._h, _ptr(s_bar), _ptr(u), _ptr(s_next), _ptr(scores), _ptr(status),
+                                        _stream()))
+        return scores
+
     # ------------------------------------------------------------ step internals
     def use_aux(self, on: bool = True, buffer=None):
         """Keep the internals of every solved step (cord_sim_set_aux): FULL
@@ -264,3 +273,16 @@ class Sim:
         off = self.offsets(ckpt_every)[kind]
         h = flat.detach().cpu().numpy()
         return [h[off[i]:off[i + 1]] for i in range(self.B)]
+
+
+def cp_radius(scores, delta: float, horizon: int):
+    """Conformal radius of a device tensor of scores for miscoverage `delta`
+    over `horizon` steps: (radius, index) as one-element device tensors
+    (index -1 with an infinite radius)."""
+    lib = L.load()
+    radius = torch.empty(1, dtype=torch.float32, device=scores.device)
+    index = torch.empty(1, dtype=torch.int32, device=scores.device)
+    L.check(lib.cord_cp_radius(_ptr(scores), int(scores.numel()), float(delta), int(horizon), _ptr(radius),
+                               _ptr(index), _stream()))
+    return radius, index
+

@@ -149,6 +149,7 @@ struct cord_sim {
     int64_t* seg_off = nullptr;
     int32_t* d_queues = nullptr;     // one work-queue counter per group
     int32_t* d_redo = nullptr;       // per (instance, step) flags of the direct linearization
+    float* cp_pred = nullptr;        // one-step predictions of cord_cp_scores (s_floats)
     void* noalloc = nullptr;         // this device's static scratch (cord_rollout_backward_noalloc)
     hipError_t noalloc_err = hipSuccess;
     int64_t n_steps = 0;             // sum T
@@ -596,6 +597,7 @@ int cord_sim_destroy(cord_sim* s) {
     if (s->kept) (void)hipFree(s->kept);
     if (s->d_queues) (void)hipFree(s->d_queues);
     if (s->d_redo) (void)hipFree(s->d_redo);
+    if (s->cp_pred) (void)hipFree(s->cp_pred);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     for (hipEvent_t ev : s->join_ev) (void)hipEventDestroy(ev);
@@ -801,6 +803,41 @@ int cord_linearize(cord_sim* s, const float* traj, const float* u, float* A, flo
         a.n_ids = (int)g.ids.size();
         CORD_HIP(launch_linearize(g.cfg, g.topo, g.nmax, g.penalty, a, a.n_ids, g.tmax, st, KeptSource{&sim_kept, s}));
     }
+    return CORD_OK;
+}
+
+int cord_cp_scores(cord_sim* s, const float* s_bar, const float* u, const float* s_next, float* scores,
+                   int32_t* inst_status, void* stream) {
+    g_err.clear();
+    if (!s || !s_bar || !s_next || !scores) return fail(CORD_EINVAL, "cord_cp_scores: NULL argument");
+    if (!u && s->info.u_floats > 0) return fail(CORD_EINVAL, "cord_cp_scores: NULL u");
+    if (s->info.max_T != 1) return fail(CORD_EINVAL, "cord_cp_scores: every calibration instance needs T = 1");
+    if (!s->cp_pred && hipMalloc(&s->cp_pred, sizeof(float) * (size_t)s->info.s_floats) != hipSuccess) {
+        s->cp_pred = nullptr;
+        (void)hipGetLastError();
+        return fail(CORD_ENOMEM, "cord_cp_scores: prediction buffer");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    KArgs a = base_args(s);
+    a.store = CORD_STORE_FINAL;
+    a.ckpt_every = 1;
+    a.s0 = s_bar; a.u = u; a.traj = s->cp_pred; a.status = inst_status;
+    int rc = launch_all(s, kOpRollout, a, st);
+    if (rc) return rc;
+    CORD_HIP(launch_cp_scores(s->d_inst, (int)s->h.size(), s->cp_pred, s_next, scores, st));
+    return CORD_OK;
+}
+
+int cord_cp_radius(const float* scores, int32_t n, double delta, int32_t horizon, float* radius, int32_t* index,
+                   void* stream) {
+    g_err.clear();
+    if (!scores || !radius || n < 1 || horizon < 1) return fail(CORD_EINVAL, "cord_cp_radius: bad arguments");
+    if (n > (1 << 16)) return fail(CORD_EUNSUPPORTED, "cord_cp_radius: at most 65536 scores");
+    const double lvl = delta / horizon;
+    if (!(lvl > 0.0 && lvl < 1.0)) return fail(CORD_EINVAL, "cord_cp_radius: delta / horizon must lie in (0, 1)");
+    const double kk = std::ceil((n + 1.0) * (1.0 - lvl) - 1e-9);
+    const int k = kk > n ? n + 1 : (int)kk;
+    CORD_HIP(launch_cp_radius(scores, n, k, radius, index, (hipStream_t)stream));
     return CORD_OK;
 }
 

@@ -38,6 +38,12 @@ constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
 // This GPU's address of that scratch (looked up once per device, with the
 // device current).
 hipError_t noalloc_scratch(int device, void** out);
+// Conformal calibration: per-instance score |x_next - x_pred|_2 over the
+// positions (both in the state layout), and the score of 1-based rank k
+// (ties by index; +inf if k > n, NaN if n is 0) with its index.
+hipError_t launch_cp_scores(const InstDev* inst, int B, const float* pred, const float* s_next, float* scores,
+                            hipStream_t s);
+hipError_t launch_cp_radius(const float* scores, int n, int k, float* radius, int32_t* rank, hipStream_t s);
 // out[b] = sum_{b' < b} (ceil(T/K) + 1) n_s over the instance table.
 hipError_t launch_ckpt_offsets(const InstDev* inst, int B, int K, int64_t* out, hipStream_t s);
 

@@ -20,4 +20,5 @@ from .gen import (  # noqa: F401
     serve_trace,
     penalty_grasp,
     compressed_rope,
+    calibration_set,
 )

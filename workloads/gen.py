@@ -286,6 +286,43 @@ def compressed_rope(n: int = 10, ratio: float = 0.75, T: int = 6, k: float = 800
                 ground=False, h=l0, s0=s0, u=u)
 
 
+def calibration_set(count: int, n: int = 11, seed: int = 1007, rho: float = 0.002, dt: float = 0.01):
+    """Perceived-state transitions (q_i, u_i, q_i+) of a rope of n nodes
+    (0.8 m, the paper's hardware rope has 11), for conformal calibration.
+    The paper's calibration data are hardware transitions that are not
+    available; these are synthetic: q_i is a random planar chain (link
+    lengths within 2 % of rest, turning angles ~ N(0, 0.3^2), height
+    U[0.05, 0.3] m), u_i ~ N(0, 0.05^2) moves the gripped node 0, and q_i+
+    is q_i dragged kinematically (node j by dt u_i exp(-j / 3)) and dropped
+    by dt^2 g; both q_i and q_i+ carry perception noise drawn uniformly
+    from the ball |e|_2 <= rho over the whole configuration.  Returns a
+    list of (Instance with T = 1, quasi-static gamma = 1 and the chain as
+    s0, q_next (n, 3))."""
+    out = []
+    length = 0.8
+    l0 = length / (n - 1)
+    for rng in _streams(seed, count):
+        ang = np.cumsum(rng.normal(0.0, 0.3, size=n - 1))
+        seg = l0 * (1.0 + rng.uniform(-0.02, 0.02, size=n - 1))
+        q = np.zeros((n, 3))
+        q[1:, 0] = np.cumsum(seg * np.cos(ang))
+        q[1:, 1] = np.cumsum(seg * np.sin(ang))
+        q[:, 2] = rng.uniform(0.05, 0.3)
+        u = rng.normal(0.0, 0.05, size=3)
+        drag = dt * u[None, :] * np.exp(-np.arange(n) / 3.0)[:, None]
+        qn = q + drag + dt * dt * np.array([0.0, 0.0, -9.81])[None, :]
+
+        def ball(d):
+            v = rng.normal(size=d)
+            return rho * rng.uniform() ** (1.0 / d) * v / np.linalg.norm(v)
+        qp = q + ball(3 * n).reshape(n, 3)
+        qnp = qn + ball(3 * n).reshape(n, 3)
+        s0 = np.concatenate([qp.ravel(), np.zeros(3 * n)])
+        inst = rope(n, length=length, dt=dt, gamma=1.0, T=1, s0=s0, u=u[None, :])
+        out.append((inst, qnp))
+    return out
+
+
 def small_rope_batch(B: int, n: int, T: int, seed: int):
     """C2-style ropes at a smaller size (parity tests)."""
     return [_c2_instance(rng, n, T) for rng in _streams(seed, B)]
