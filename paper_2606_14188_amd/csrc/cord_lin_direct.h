@@ -3,8 +3,12 @@
 // For a rope every operator of the step derivative (the stage-1 Hessian H,
 // the stage-2 matrix K = H + N^T Lam N and J = H - W + C - R of eq.
 // (diff-sim)) couples a particle only with its neighbours up to distance 2
-// (stretch springs at distance 1, the bending stencil at distance 2).  In the
-// 3n scalar unknowns each is a band matrix of half-bandwidth 8, so one
+// (stretch springs at distance 1, the bending stencil at distance 2).  The
+// bending coupling of particles two apart, k_b I, is diagonal, so in the 3n
+// scalar unknowns (xyz of particle p at 3p..3p+2) H and K are band matrices
+// of half-bandwidth 6 (a full 3x3 block two particles away would make it
+// 8), and so are their band Cholesky factors; G = C - R - W couples
+// neighbouring particles only (9 scalar taps per row).  So one
 // workgroup per (instance, step) restores (or solves again) the step,
 // assembles the bands in LDS, factors H_ff = L L^T and K_ff = U U^T (U upper
 // triangular: the Cholesky factor of the index-reversed matrix) with one
@@ -47,7 +51,8 @@
 
 namespace cord {
 
-constexpr int kBand = 8;   // half-bandwidth of H, K, J in scalar unknowns
+constexpr int kBand = 6;   // half-bandwidth of H, K and of their factors in scalar unknowns
+constexpr int kTri = kBand * (kBand + 1) / 2;   // entries of the trailing window of a factorization step
 constexpr int kGB = 5;     // half-bandwidth of G = C - R - W
 constexpr int kBlk1 = 24;  // rows per unrolled block of sweep 1
 constexpr int kBlk2 = 24;  // rows per unrolled block of sweeps 2 and 3 (they load)
@@ -56,7 +61,7 @@ constexpr int kPf = 23;    // rows of prefetch distance for the kept vector
 constexpr int kPfR = 24;   // slots of the prefetch ring
 // A row's window slot is its position in the block mod kWin (mod kPfR for
 // the prefetch ring), a constant of the unrolled body; the windows hold the
-// last 8 values (L and U solves) and the last 11 (eps for the G product).
+// last kBand values (L and U solves) and the last 11 (eps for the G product).
 static_assert(kWin > 2 * kGB && kWin > kBand && kBlk1 % kWin == 0 && kBlk2 % kWin == 0,
               "windows must divide the blocks");
 static_assert(kPf < kPfR && kBlk2 % kPfR == 0 && kBlk1 >= 2 * kBand && kBlk2 >= 2 * kBand,
@@ -70,15 +75,15 @@ template <int NMAX>
 struct LinLds {
     static constexpr int N3 = 3 * NMAX;
     // inside the solver's region
-    static constexpr int HB = 0;                  // H_el(i, i-m), m = 0..8 [i][9] (H - M/dt^2 on free rows)
+    static constexpr int HB = 0;                  // H_el(i, i-m), m = 0..kBand [i][9] (H - M/dt^2 on free rows)
     static constexpr int NL = HB + N3 * 9;        // (w n n^T) row i, same-particle columns [i][3]
     static constexpr int SA = NL + N3 * 3;
     // after the solver's region
-    static constexpr int LC = 0;                  // L(k+m, k), m = 1..8   [k][8]
+    static constexpr int LC = 0;                  // L(k+m, k), m = 1..kBand   [k][8]
     static constexpr int LI = LC + N3 * 8;        // 1 / L(k, k)
     static constexpr int UW = LI + N3;            // U(i-m, i) at [N-1-i][m-1]
     static constexpr int UD = UW + N3 * 8;        // 1 / U(i, i) at [N-1-i]
-    static constexpr int UR = UD + N3;            // U(i, i+m), m = 1..8   [i][8]
+    static constexpr int UR = UD + N3;            // U(i, i+m), m = 1..kBand   [i][8]
     static constexpr int GB = UR + N3 * 8;        // G(i, i-5+q), q = 0..10 [i][12]
     static constexpr int RF = GB + N3 * 12;       // 1 if row i is free
     static constexpr int TOTAL = RF + N3;
@@ -123,12 +128,13 @@ __device__ __forceinline__ void sym_to_full(const float s[6], float m[3][3]) {
     m[2][0] = s[2]; m[2][1] = s[4]; m[2][2] = s[5];
 }
 
-// Banded Cholesky (half-bandwidth 8) by one wavefront, in place:
+// Banded Cholesky (half-bandwidth kBand) by one wavefront, in place:
 // C[k][m-1] = A(k+m, k) -> L(k+m, k),  Dg[k] = A(k, k) -> 1 / L(k, k).
 // Right-looking; at step k every lane has one job and writes one value:
-// lanes 0..35 apply the rank-1 update to one of the 36 entries of the
-// trailing 8x8 window, lanes 36..43 scale one entry of column k, lane 44
-// stores the pivot's inverse square root, the others write to their own
+// lanes 0..kTri-1 apply the rank-1 update to one of the kTri entries of
+// the trailing kBand x kBand window, the next kBand lanes scale one entry
+// of column k, the next one stores the pivot's inverse square root, the
+// others write to their own
 // slot of `sink` (64 floats of LDS not in use during the factorization).
 // All LDS reads of a step (at addresses inside the workgroup's LDS for
 // every lane) are issued before its write, and the entries a step writes
@@ -140,18 +146,18 @@ __device__ __forceinline__ void sym_to_full(const float s[6], float m[3][3]) {
 // 1 so that the sweeps stay finite).
 __device__ __forceinline__ bool band_cholesky(float* C, float* Dg, int N, float* sink) {
     const int lane = (int)threadIdx.x & 63;
-    // lanes 0..35 -> (a, b), 1 <= a <= b <= 8, column-major over b
+    // lanes 0..kTri-1 -> (a, b), 1 <= a <= b <= kBand, column-major over b
     int ua = 1, ub = 1;
-    if (lane < 36) {
+    if (lane < kTri) {
         int idx = lane, b = 1;
         while (b <= kBand && idx >= b) { idx -= b; ++b; }
         ub = b;
         ua = idx + 1;
     }
-    const bool upd = lane < 36;
-    const bool scl = lane >= 36 && lane < 36 + kBand;
-    const bool piv = lane == 36 + kBand;
-    const int sm = scl ? lane - 35 : 0;   // column entry m of a scaling lane
+    const bool upd = lane < kTri;
+    const bool scl = lane >= kTri && lane < kTri + kBand;
+    const bool piv = lane == kTri + kBand;
+    const int sm = scl ? lane - kTri + 1 : 0;   // column entry m of a scaling lane
     // per-lane offsets relative to step k (floats): reads xa, xb from column
     // k, t from the update target; the write goes to w (stride ws) or sink
     const int ra = upd ? ua - 1 : (scl ? sm - 1 : 0);
@@ -215,7 +221,7 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
     extern __shared__ float lds[];
     const InstDev& I = a.inst[id];
     if (t >= I.T) return;
-    Solver<kRope, NT, 1, NOBS> S;
+    Solver<kRope, NT, 1, NOBS, false> S;
     S.init(I, lds);
     const int n = I.n, ns = I.n_s, nu = I.n_u, N = 3 * n;
     const float kap = I.kappa_bwd, dt = I.dt, idt = 1.0f / I.dt, gam = I.gamma, mdt2 = S.mdt2;
@@ -428,6 +434,13 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
             }
         }
     }
+    // flag: this step goes to the iterative kernel.  It lives in the
+    // solver's reduction slots (not in use any more; HB and NL end below
+    // them): a static __shared__ variable would shift the dynamic LDS base
+    // off the 16-byte alignment of the band rows' 128-bit reads.
+    volatile int* const redone = reinterpret_cast<volatile int*>(S.rb) + 48;
+    static_assert(LL::SA <= 12 * NT, "the reduction slots must lie above HB and NL");
+    if (threadIdx.x == 0) *redone = 0;
     __syncthreads();
     // ---------------------------------------------------------- factorizations
     {
@@ -442,11 +455,16 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
         // (e.g. a compressed rope); the step is done again by the iterative
         // kernel when the caller keeps per-step flags, else reported
         if (!ok && (threadIdx.x & 63) == 0) {
-            if (a.redo) a.redo[I.t_off + t] = 1;
-            else if (a.status) atomicMax(&a.status[id], kStNotPD);
+            if (a.redo) {
+                a.redo[I.t_off + t] = 1;
+                *redone = 1;
+            } else if (a.status) {
+                atomicMax(&a.status[id], kStNotPD);
+            }
         }
     }
     __syncthreads();
+    if (*redone) return;   // the whole workgroup: the iterative kernel writes this step
     // row layout of U for the descending solve: UR[i][m-1] = U(i, i+m)
     for (int i = threadIdx.x; i < N; i += NT)
 #pragma unroll
@@ -475,7 +493,7 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
         // wavefront (wave-uniform: kept in a scalar register)
         const int i0 = __builtin_amdgcn_readfirstlane(max(0, (int)(threadIdx.x & ~63) - kBand));
         // rows that can carry a column-local right-hand-side term for some
-        // column of this wavefront: |row - j| <= 8 for j in j0..j0+63
+        // column of this wavefront: |row - j| <= kBand for j in j0..j0+63
         const int jl0 = i0, jl1 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63) + 63 + kBand);
         // kept vector of this lane: row r at byte rS-base + vS + r krow;
         // wbase + (r - i0) krow + wl addresses row r >= i0 for a window
@@ -616,13 +634,19 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
                         const bool same = (uint32_t)(cj - dq) <= 2u;
                         r = ((dq == dgc) ? gv : 0.f) - (same ? nl : 0.f) - ((dq == dqc) ? hv : 0.f);
                     }
-                    // G(m, m-5..m+5) eps; e[(u - qq)] holds eps_{mrow - 5 + qq}
+                    // G(m, m-5..m+5) eps; e[(u - qq)] holds eps_{mrow - 5 + qq}.
+                    // Row mrow = 3p + rc couples with particles p-1, p, p+1
+                    // only: taps qq = 2-rc .. 10-rc (the others are zero).
+                    // ib is a multiple of 3, so rc = (kGB + v) mod 3 is a
+                    // constant of the unrolled body.
+                    const int rc = (kGB + v) % 3;
                     const float4 g0 = *reinterpret_cast<const float4*>(GBb + v * 12);
                     const float4 g1 = *reinterpret_cast<const float4*>(GBb + v * 12 + 4);
                     const float4 g2 = *reinterpret_cast<const float4*>(GBb + v * 12 + 8);
                     const float gr[12] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w, g2.x, g2.y, g2.z, g2.w};
 #pragma unroll
-                    for (int qq = 2 * kGB; qq >= 0; --qq) r += gr[qq] * e[(u - qq + kWin) % kWin];
+                    for (int qq = 2 * kGB; qq >= 0; --qq)
+                        if (qq >= 2 - rc && qq <= 2 * kGB - rc) r += gr[qq] * e[(u - qq + kWin) % kWin];
                     if (loc) r *= RFb[v];   // (G rows of gripped particles are zero)
                     const float4 q0 = *reinterpret_cast<const float4*>(URb + v * 8);
                     const float4 q1 = *reinterpret_cast<const float4*>(URb + v * 8 + 4);
@@ -715,6 +739,7 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
             }
         }
     }
+    // a step done again by the iterative kernel reports that kernel's status
     if (threadIdx.x == 0 && a.status) atomicMax(&a.status[id], S.status);
     if (threadIdx.x == 0 && a.counters)
         for (int i = 0; i < 4; ++i) atomicAdd(&a.counters[4 * id + i], S.cnt[i]);

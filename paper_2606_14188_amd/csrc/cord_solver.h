@@ -217,7 +217,11 @@ template <int NT, int PPT>
 constexpr int lds_floats() { return 12 * NT * PPT + 64 + 16 * kMaxGrip; }
 
 // ----------------------------------------------------------------- solver
-template <int TOPO, int NT, int PPT, int NOBS>
+// FALLBACK = false compiles the solves without MINRES and the hard-contact
+// polish (for the direct rope linearization, whose band factorizations
+// detect an indefinite dF/dq* themselves and hand such steps to the
+// iterative kernel, which has both).
+template <int TOPO, int NT, int PPT, int NOBS, bool FALLBACK = true>
 struct Solver {
     static constexpr int NM = NT * PPT;
     static constexpr int NS = Topo<TOPO>::NS;
@@ -798,8 +802,12 @@ struct Solver {
     // residual norm is then no norm).  Flags NOT_PD only if MINRES fails.
     template <bool CONTACT>
     __device__ __forceinline__ void solve(const float b[PPT][3], float xs[PPT][3], float rtol) {
-        if (bmin(pcpd) > 0.f && pcg<CONTACT>(b, xs, rtol)) return;
-        if (!minres<CONTACT>(b, xs, rtol)) status = max(status, kStNotPD);
+        if constexpr (!FALLBACK) {
+            if (!pcg<CONTACT>(b, xs, rtol)) status = max(status, kStNotPD);
+        } else {
+            if (bmin(pcpd) > 0.f && pcg<CONTACT>(b, xs, rtol)) return;
+            if (!minres<CONTACT>(b, xs, rtol)) status = max(status, kStNotPD);
+        }
     }
 
     // Psi(y + DL) - Psi(y) with DL mirrored in LDS, in cancellation-free form
@@ -1130,7 +1138,9 @@ struct Solver {
             }
         }
         if (!conv) status = max(status, kStQP);
-        else if (hard) hard_polish();
+        else if constexpr (FALLBACK) {
+            if (hard) hard_polish();
+        }
     }
 
     // Hard contact: the interior point ends with a small positive lam * gap
