@@ -347,6 +347,19 @@ int cord_linearize(cord_sim* sim, const float* traj, const float* u, float* A, f
                    const cord_jvp* jvp, int32_t* inst_status, void* stream);
 
 /*
+ * Counters of the dense rope linearization since the simulator was created
+ * (host array of 2): out2[0] steps whose scratch slot was found shared
+ * by two workgroups resident at the same time (each such step is done
+ * again by the row-by-row kernel, so A_t stays exact; nonzero would mean
+ * the hardware slot key does not separate resident workgroups), out2[1]
+ * steps done again by that kernel for any reason (a non-positive pivot
+ * of a band factor, an indefinite dF/dq* of Sec. 4.1 "Differentiating
+ * Through Simulation", or a shared slot).  Synchronizes the device.
+ * Errors: CORD_EINVAL, CORD_EHIP.
+ */
+int cord_sim_lin_stats(cord_sim* sim, int64_t* out2);
+
+/*
  * Sizes in bytes of the public structs, for bindings that mirror them:
  * out[0] cord_params, out[1] cord_instance_desc, out[2] cord_sim_info_t,
  * out[3] cord_rollout_opts, out[4] cord_backward_opts, out[5] cord_jvp.

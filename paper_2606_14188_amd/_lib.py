@@ -92,6 +92,7 @@ _EXPORTS = {
                                         c_void_p, POINTER(BackwardOpts), c_void_p]),
     "cord_rollout_backward_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                                 c_void_p, POINTER(BackwardOpts), c_void_p]),
+    "cord_sim_lin_stats": (c_int32, [c_void_p, POINTER(c_int64)]),
     "cord_cp_scores": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "cord_cp_radius": (c_int32, [c_void_p, c_int32, ctypes.c_double, c_int32, c_void_p, c_void_p, c_void_p]),
     "cord_linearize": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(Jvp),

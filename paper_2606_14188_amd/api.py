@@ -179,6 +179,13 @@ class Sim:
                                         _ptr(status), _stream()))
         return (A if dense else None), (Bm if want_B else None), out
 
+    def lin_stats(self):
+        """Direct-linearization counters since creation: {"slot_overlaps",
+        "steps_redone"} (synchronizes the device)."""
+        out = (c_int64 * 2)()
+        L.check(self.lib.cord_sim_lin_stats(self._h, out))
+        return {"slot_overlaps": int(out[0]), "steps_redone": int(out[1])}
+
     # ------------------------------------------------------------ conformal calibration
     def cp_scores(self, s_bar, u, s_next, status=None):
         """Nonconformity scores |q+ - f(q, u)|_2 of a calibration set (one

@@ -150,6 +150,7 @@ struct cord_sim {
     int32_t* d_queues = nullptr;     // one work-queue counter per group
     int32_t* d_redo = nullptr;       // per (instance, step) flags of the direct linearization
     float* cp_pred = nullptr;        // one-step predictions of cord_cp_scores (s_floats)
+    uint32_t* lin_stats = nullptr;   // direct linearization counters (scratch-slot overlaps, steps redone)
     void* noalloc = nullptr;         // this device's static scratch (cord_rollout_backward_noalloc)
     hipError_t noalloc_err = hipSuccess;
     int64_t n_steps = 0;             // sum T
@@ -320,6 +321,14 @@ float* sim_kept(void* ctx, size_t floats) {
         if (s->kept) { (void)hipFree(s->kept); s->kept = nullptr; s->kept_floats = 0; }
         if (hipMalloc(&s->kept, sizeof(float) * floats) != hipSuccess) {
             (void)hipGetLastError();   // run without the scratch
+            s->kept = nullptr;
+            return nullptr;
+        }
+        // the guard words after the slots start at zero (every use of a
+        // slot returns its busy count to zero; the start counts only grow)
+        if (hipMemset(s->kept, 0, sizeof(float) * floats) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(s->kept);
             s->kept = nullptr;
             return nullptr;
         }
@@ -598,6 +607,7 @@ int cord_sim_destroy(cord_sim* s) {
     if (s->d_queues) (void)hipFree(s->d_queues);
     if (s->d_redo) (void)hipFree(s->d_redo);
     if (s->cp_pred) (void)hipFree(s->cp_pred);
+    if (s->lin_stats) (void)hipFree(s->lin_stats);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     for (hipEvent_t ev : s->join_ev) (void)hipEventDestroy(ev);
@@ -797,12 +807,31 @@ int cord_linearize(cord_sim* s, const float* traj, const float* u, float* A, flo
             CORD_HIP(launch_fill_i32(s->d_redo, s->n_steps, 0, st));
             a.redo = s->d_redo;
         }
+        if (!s->lin_stats) {
+            if (hipMalloc(&s->lin_stats, 4 * sizeof(uint32_t)) != hipSuccess ||
+                hipMemset(s->lin_stats, 0, 4 * sizeof(uint32_t)) != hipSuccess) {
+                (void)hipGetLastError();
+                if (s->lin_stats) (void)hipFree(s->lin_stats);
+                s->lin_stats = nullptr;
+            }
+        }
+        a.lin_stats = s->lin_stats;
     }
     for (const Group& g : s->groups) {
         a.ids = g.d_ids;
         a.n_ids = (int)g.ids.size();
         CORD_HIP(launch_linearize(g.cfg, g.topo, g.nmax, g.penalty, a, a.n_ids, g.tmax, st, KeptSource{&sim_kept, s}));
     }
+    return CORD_OK;
+}
+
+int cord_sim_lin_stats(cord_sim* s, int64_t* out2) {
+    g_err.clear();
+    if (!s || !out2) return fail(CORD_EINVAL, "cord_sim_lin_stats: NULL argument");
+    uint32_t h[2] = {0, 0};
+    if (s->lin_stats) CORD_HIP(hipMemcpy(h, s->lin_stats, sizeof(h), hipMemcpyDeviceToHost));
+    out2[0] = h[0];
+    out2[1] = h[1];
     return CORD_OK;
 }
 

@@ -74,6 +74,7 @@ struct KArgs {
     int32_t aux_mode;          // 1: rollout writes them; 2: backward / linearize read them
     float* kept;               // direct rope linearization: scratch slots, or null
     int32_t kept_tg;           // workgroup slots per CU in that scratch table
+    uint32_t* lin_stats;       // direct linearization counters: [0] scratch-slot overlaps, [1] steps redone
     int32_t* redo;             // per (instance, step) at t_off + t: the direct linearization sets 1 where a
                                // band factor met a non-positive pivot; the iterative linearize kernel run
                                // with this set does only those steps (null: every step)

@@ -200,16 +200,22 @@ constexpr size_t kept_slot_floats() { return (size_t)NT * 3 * NMAX; }
 // Scratch slots: XCDs x shader engines x CU ids x workgroup slots per CU.
 constexpr int kSlotXcc = 8, kSlotSe = 4, kSlotCu = 16;
 __host__ __device__ constexpr int kept_slots(int wg_per_cu) { return kSlotXcc * kSlotSe * kSlotCu * wg_per_cu; }
+// After the slots: two guard words per slot (workgroups using it now,
+// workgroups that have started on it), zero when the table is allocated.
+__host__ __device__ constexpr size_t kept_guard_floats(int wg_per_cu) { return 2 * (size_t)kept_slots(wg_per_cu); }
 
 // This workgroup's scratch slot from the hardware registers (wave-uniform),
-// or -1 if a field lies outside the table.  HW_ID: CU_ID bits 8-11, SE_ID
-// bits 13-15, TG_ID (workgroup slot on the CU) bits 16-19.
+// or -1 if a field lies outside the table.  HW_ID: CU_ID bits 8-11, SH_ID
+// bit 12 (must be 0: it is not part of the key), SE_ID bits 13-15, TG_ID
+// (workgroup slot on the CU) bits 16-19.  Whether two resident workgroups
+// ever share a slot is not left to this mapping alone: the guard words
+// detect any overlap in time (see lin_direct_item).
 __device__ __forceinline__ int hw_slot(int wg_per_cu) {
     unsigned hw, xcc;
     asm volatile("s_getreg_b32 %0, hwreg(HW_REG_HW_ID)" : "=s"(hw));
     asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
-    const int cu = (hw >> 8) & 15, se = (hw >> 13) & 7, tg = (hw >> 16) & 15, x = xcc & 15;
-    if (x >= kSlotXcc || se >= kSlotSe || tg >= wg_per_cu) return -1;
+    const int cu = (hw >> 8) & 15, sh = (hw >> 12) & 1, se = (hw >> 13) & 7, tg = (hw >> 16) & 15, x = xcc & 15;
+    if (x >= kSlotXcc || se >= kSlotSe || tg >= wg_per_cu || sh != 0) return -1;
     return ((x * kSlotSe + se) * kSlotCu + cu) * wg_per_cu + tg;
 }
 
@@ -464,7 +470,10 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
         }
     }
     __syncthreads();
-    if (*redone) return;   // the whole workgroup: the iterative kernel writes this step
+    if (*redone) {         // the whole workgroup: the iterative kernel writes this step
+        if (threadIdx.x == 0 && a.lin_stats) atomicAdd(a.lin_stats + 1, 1u);
+        return;
+    }
     // row layout of U for the descending solve: UR[i][m-1] = U(i, i+m)
     for (int i = threadIdx.x; i < N; i += NT)
 #pragma unroll
@@ -499,6 +508,29 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
         // wbase + (r - i0) krow + wl addresses row r >= i0 for a window
         const int wf = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
         const int slot = a.kept ? hw_slot(a.kept_tg) : -1;
+        // guard of the slot: thread 0 marks it busy and counts a start; a
+        // workgroup that finds it busy leaves it alone and hands its step to
+        // the iterative kernel (the one using it detects the overlap at its
+        // end, from the start count, and does the same)
+        uint32_t* const guard = slot >= 0 ? reinterpret_cast<uint32_t*>(
+            a.kept + (size_t)kept_slots(a.kept_tg) * kept_slot_floats<NT, NMAX>()) + 2 * slot : nullptr;
+        uint32_t my_start = 0;
+        if (guard) {
+            if (threadIdx.x == 0) {
+                const uint32_t busy = atomicAdd(guard, 1u);
+                my_start = atomicAdd(guard + 1, 1u);
+                *redone = busy != 0u ? 1 : 0;
+            }
+            __syncthreads();
+            if (*redone) {
+                if (threadIdx.x == 0) {
+                    atomicSub(guard, 1u);
+                    if (a.redo) a.redo[I.t_off + t] = 1;
+                    if (a.lin_stats) { atomicAdd(a.lin_stats, 1u); atomicAdd(a.lin_stats + 1, 1u); }
+                }
+                return;
+            }
+        }
         const float* kbase;
         uint32_t kbytes, vS, krow, wl;
         const float* wbase;
@@ -724,6 +756,22 @@ __device__ __forceinline__ void lin_direct_item(const KArgs& a, const int id, co
                 } else {
 #pragma unroll
                     for (int u = 0; u < kBlk2; ++u) row(u, true);
+                }
+            }
+        }
+        // end of the slot's use: another workgroup that started on it since
+        // (or was on it at the start) may have overwritten the kept vectors,
+        // so the step is handed to the iterative kernel, which runs after
+        // this launch and rewrites all of A_t and B_t for it
+        if (guard) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const uint32_t starts = atomicAdd(guard + 1, 0u);
+                const uint32_t busy = atomicSub(guard, 1u);
+                if (starts != my_start + 1u || busy != 1u) {
+                    if (a.redo) a.redo[I.t_off + t] = 1;
+                    if (a.lin_stats) { atomicAdd(a.lin_stats, 1u); atomicAdd(a.lin_stats + 1, 1u); }
+                    if (!a.redo && a.status) atomicMax(&a.status[id], kStNotPD);
                 }
             }
         }

@@ -57,7 +57,7 @@ size_t linearize_rope_direct_scratch(int nmax, int* wg_per_cu) {
     const int r = per_cu(nmax, c);
     if (r < 1) return 0;
     *wg_per_cu = r;
-    return (size_t)kept_slots(r) * c.slot;
+    return (size_t)kept_slots(r) * c.slot + kept_guard_floats(r);
 }
 
 hipError_t linearize_rope_direct(int nmax, const KArgs& a, int nblk, int tmax, hipStream_t s) {

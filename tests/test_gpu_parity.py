@@ -496,6 +496,8 @@ def test_linearize_concurrent_streams():
     torch.cuda.synchronize()
     for (A1, B1), (A2, B2) in zip(ref, out):
         assert torch.equal(A1, A2) and torch.equal(B1, B2)
+    for sim, _, _ in runs:
+        assert sim.lin_stats()["slot_overlaps"] == 0
 
 
 def test_backward_and_linearize_overlap_on_two_sims():
@@ -547,6 +549,11 @@ def test_c2_linearize_full_size_sampled():
     A, Bm, _ = sim.linearize(traj, u, status=status)
     torch.cuda.synchronize()
     assert (status.cpu().numpy() == 0).all()
+    # no two resident workgroups shared a scratch slot, and no step needed
+    # the row-by-row kernel
+    stats = sim.lin_stats()
+    print("linearization counters", stats, flush=True)
+    assert stats == {"slot_overlaps": 0, "steps_redone": 0}
     offA, offB, offT = sim.offsets()["A"], sim.offsets()["B"], sim.offsets()["traj"]
     for j, t in [(0, 0), (1, 99), (517, 50), (1023, 7), (700, 93)]:
         inst = insts[j]

@@ -168,6 +168,41 @@ def test_full_size_request_sampled():
         srv.close()
 
 
+def test_cloth_request_matches_oracle():
+    """A cloth planning request (8x8 nodes, two corners gripped, 6-D
+    controls) from caller-given candidates: every candidate's final cost,
+    the winner, its controls and its trajectory against the oracle planner
+    run through the same projected gradient steps."""
+    from paper_2606_14188_amd.serve import Server
+    inst = W.small_cloth_batch(1, 8, 8, 6, seed=940)[0]
+    rng = np.random.default_rng(41)
+    C, iters, step, umax, reg = 4, 3, 2.0, 0.5, 1e-3
+    u_init = inst.u[None] + 0.02 * rng.normal(size=(C,) + inst.u.shape)
+    goal = inst.s0[3 * (inst.n - 1):3 * inst.n] + np.array([0.02, -0.01, 0.03])
+    srv = Server(hbm_budget=1 << 30, max_slots=2)
+    try:
+        t = srv.submit(inst, goal_node=inst.n - 1, goal=goal, n_cand=C, iters=iters, step=step, u_max=umax,
+                       u_reg=reg, u_init=u_init)
+        r = srv.wait(t, 120000)
+        assert r is not None and r.status == 0 and r.sim_status == 0
+        ref = planner.plan(inst, u_init, inst.n - 1, goal, iters, step, umax, reg)
+        print("costs gpu", r.costs, "oracle", ref["costs"], flush=True)
+        np.testing.assert_allclose(r.costs, ref["costs"], rtol=2e-4)
+        b = r.best
+        assert ref["costs"][b] <= ref["costs"].min() * (1 + 2e-4)
+        eu = np.linalg.norm(r.u - ref["u"][b]) / np.linalg.norm(ref["u"][b] - u_init[b])
+        print(f"winner {b}: controls err (relative to the distance moved) {eu:.2e}", flush=True)
+        assert eu <= GRAD_TOL
+        # the winner's trajectory is the rollout of its (GPU) controls
+        jb, tr = _cost(inst, r.u.astype(np.float64), inst.n - 1, goal, reg)
+        ex, ev = state_errors(r.traj, tr, inst.n)
+        assert ex <= STATE_TOL and ev <= STATE_TOL, (ex, ev)
+        assert abs(r.costs[b] - jb) <= 2e-4 * jb
+        srv.release(t)
+    finally:
+        srv.close()
+
+
 def test_winner_linearization_matches_oracle():
     from paper_2606_14188_amd.serve import Server
     inst = _rope(n=24, T=6, seed=910)
