@@ -193,10 +193,18 @@ def test_cloth_request_matches_oracle():
         eu = np.linalg.norm(r.u - ref["u"][b]) / np.linalg.norm(ref["u"][b] - u_init[b])
         print(f"winner {b}: controls err (relative to the distance moved) {eu:.2e}", flush=True)
         assert eu <= GRAD_TOL
-        # the winner's trajectory is the rollout of its (GPU) controls
-        jb, tr = _cost(inst, r.u.astype(np.float64), inst.n - 1, goal, reg)
+        # the winner's trajectory is the rollout of its (GPU) controls; a
+        # slow cloth (|v| <= 8 cm/s at positions up to 0.38 m, dt = 2 ms)
+        # sits at the FP32 floor of the velocity bar: the oracle's own steps
+        # with the state rounded to FP32 in between drift by 1e-4 in v, so
+        # the GPU is held to three times that drift (as in the mixed batch)
+        from tests.oracle_pool import fp32_storage_drift
+        uw = r.u.astype(np.float64)
+        jb, tr = _cost(inst, uw, inst.n - 1, goal, reg)
         ex, ev = state_errors(r.traj, tr, inst.n)
-        assert ex <= STATE_TOL and ev <= STATE_TOL, (ex, ev)
+        sx, sv = fp32_storage_drift(inst.replace(u=uw), tr)
+        print(f"winner trajectory: x {ex:.2e} v {ev:.2e}; FP32-storage drift x {sx:.2e} v {sv:.2e}", flush=True)
+        assert ex <= max(STATE_TOL, 3 * sx) and ev <= max(STATE_TOL, 3 * sv), (ex, ev)
         assert abs(r.costs[b] - jb) <= 2e-4 * jb
         srv.release(t)
     finally:

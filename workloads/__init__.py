@@ -21,4 +21,5 @@ from .gen import (  # noqa: F401
     penalty_grasp,
     compressed_rope,
     calibration_set,
+    lift_rope_envs,
 )

@@ -323,6 +323,31 @@ def calibration_set(count: int, n: int = 11, seed: int = 1007, rho: float = 0.00
     return out
 
 
+def lift_rope_envs(B: int, n: int = 12, seed: int = 1008, kappa_fwd: float = 0.0):
+    """Environments of a synthetic lift-rope task (the paper's first task: a
+    pair of grippers must make contact with the rope to activate the
+    holonomic constraint, then lift it).  Each is a rope of n nodes (0.5 m)
+    lying just above the ground (z = 2 mm, seeded lateral waviness
+    N(0, (5 mm)^2)), with penalty grippers for nodes 0 and n - 1 that start
+    U[1.5, 3] cm above their nodes (activation exp(-|c| / 1 cm), so the grasp
+    is weak until a gripper comes down), one step per instance (T = 1: a
+    policy closes the loop between steps), hard contact forward
+    (kappa_fwd = 0) and smoothed gradients (kappa_bwd from a 1 mm width):
+    the paper's surrogate-gradient mode."""
+    out = []
+    for rng in _streams(seed, B):
+        y = rng.normal(0.0, 0.005, size=n)
+        base = rope(n, length=0.5, z0=0.002, T=1, grip_nodes=(0, n - 1), kappa_fwd=kappa_fwd)
+        x = base.s0[:3 * n].reshape(n, 3).copy()
+        x[:, 1] = y
+        g0 = x[[0, n - 1]] + np.stack([np.zeros(2), np.zeros(2), rng.uniform(0.015, 0.03, size=2)], axis=1)
+        s0 = np.concatenate([x.ravel(), np.zeros(3 * n), g0.ravel()])
+        inst = base.replace(grip_mode="penalty", D_max=100.0 * base.mass / base.dt ** 2, kappa_h=0.01,
+                            r_g=0.005, s0=s0)
+        out.append(inst)
+    return out
+
+
 def small_rope_batch(B: int, n: int, T: int, seed: int):
     """C2-style ropes at a smaller size (parity tests)."""
     return [_c2_instance(rng, n, T) for rng in _streams(seed, B)]
