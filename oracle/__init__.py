@@ -23,6 +23,9 @@ step         one time step (stage 1 + stage 2) and rollouts
 derivatives  per-step JVP / VJP, dense A_t / B_t, rollout gradient
 planner      reference projected-gradient planner (cost, gradient, step, argmin)
 conformal    conformal radius of the one-step model error (scores, order statistic)
+apg          the step as a differentiable torch layer for analytical policy gradients
+sls          output-feedback SLS stage 3: Kalman recursion and its associative scan,
+             observer propagations, assembly of the closed-loop responses, tubes
 """
 STATUS_OK = 0
 STATUS_NEWTON_NOCONV = 1
