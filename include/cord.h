@@ -548,6 +548,79 @@ int cord_plan_release(cord_server* srv, uint64_t ticket);
  * running now, peak queue depth, bytes in use (host array of 8 int64). */
 int cord_server_stats(cord_server* srv, int64_t* out8);
 
+/* ---------------------------------------------------------------- output-feedback SLS */
+/*
+ * Stage 3 of the output-feedback SLS decomposition (Sec. 4.2,
+ * "Simulator-Informed GPU-Parallel Output Feedback SLS") for a batch of B
+ * nominal trajectories of N steps, state size n, input size m, with the
+ * perception returning the full state (C = I, Sec. 4.4).  Conventions:
+ * x_{j+1} = A_j x_j + B_j u_j + E_j w_j and y_{j+1} = x_j + F_j e_j (the
+ * measurement of x_j has index j + 1).  All buffers are device memory,
+ * row-major, instance-major, owned by the caller:
+ *   A, E, F      float[B][N][n][n]   (A as written by cord_linearize for
+ *                                     instances of equal n_s and T = N)
+ *   Bm           float[B][N][n][m]   K  float[B][N+1][m][n]
+ *   Xi           float[B][n][n]      initial uncertainty
+ *   Pi           float[B][N+1][n][n] L  float[B][N][n][n], L[j] = L_{j+1}
+ *   horizon operators: dense float[B][(N+1) r][(N+1) n] with block (k, j)
+ *   at rows k r, columns j n, where r = n for state rows and m for input
+ *   rows; the blocks right of the block diagonal are written as zeros.
+ * Calls are stream-ordered on `stream` (NULL = default stream); calls on one
+ * handle share its workspace and must not overlap.
+ *
+ * cord_sls_create: a handle for (B, N, n, m) and its device workspace
+ * (about 2 B (N+1)^2 n^2 + 12 B (N+1) n^2 floats).  Errors: CORD_EINVAL,
+ * CORD_EUNSUPPORTED (n > 1024), CORD_ETOOBIG (one horizon operator above
+ * 64 GiB), CORD_ENOMEM.
+ *
+ * cord_sls_kalman: the Kalman recursion (eq. kalman_recursions),
+ * Pi_0 = Xi Xi^T, L_{j+1} = -(F_j F_j^T + Pi_j)^{-1} Pi_j A_j^T,
+ * Pi_{j+1} = E_j E_j^T + A_j Pi_j A_j^T + A_j Pi_j L_{j+1}, either
+ * CORD_SLS_SERIAL (one workgroup per instance steps through the horizon) or
+ * CORD_SLS_SCAN (the associative scan of eqs. combination_rules and
+ * initialization, ceil(log2(N+1)) rounds, then all gains at once).
+ * status: device int32[B], CORD_ST_NOT_PD where a solve met a zero or
+ * non-finite pivot.  Errors: CORD_EINVAL, CORD_EHIP.
+ *
+ * cord_sls_observer: the observer responses (eq. backward_propagations):
+ * Phx[k][j] = Ahat_{k-1} .. Ahat_j with Ahat_j = A_j + L_{j+1}^T, Phx[k][k]
+ * = I, and Phy[k][j] = Phx[k][j] L_j^T for 1 <= j <= k (column block 0 is
+ * zero); both (N+1) n x (N+1) n.  The products are formed by doubling along
+ * the block diagonals: one GEMM per block, 2 ceil(log2 N) launches.
+ *
+ * cord_sls_state_feedback: the responses of u_j = K_j x_j, Pbx = (I - Z(A +
+ * B K))^{-1} ((N+1) n square) and Pbu = blkdiag(K) Pbx ((N+1) m x (N+1) n):
+ * a stand-in for stage 2 of the decomposition (GPU-SLS, prior work the paper
+ * builds on), with the same kernels as cord_sls_observer.
+ *
+ * cord_sls_assemble: with M = I - ZA, the closed-loop responses
+ * Pxw = Pbx + Phx - Pbx M Phx,  Puw = Pbu (I - M Phx),
+ * Pxe = Phy - Pbx M Phy,        Pue = -Pbu M Phy,
+ * as block-triangular GEMMs (only the nonzero block range of each output
+ * tile is summed).
+ *
+ * cord_sls_tubes: the tube widths of the tightening constraints (eq.
+ * of_optimization) for unit-ball w_j and e_j,
+ * tau[k] = sum_{j<k} rownorm(Pxw[k][j+1] E_j) + rownorm(Pxe[k][j+1] F_j)
+ * (float[B][N+1][n]; tau[0] = 0), and likewise tau_u from Puw and Pue
+ * (float[B][N+1][m]) when tau_u is not NULL.  Errors: CORD_EINVAL,
+ * CORD_EHIP.
+ */
+typedef struct cord_sls cord_sls;
+#define CORD_SLS_SERIAL 0
+#define CORD_SLS_SCAN   1
+int cord_sls_create(int32_t batch, int32_t horizon, int32_t n, int32_t n_u, cord_sls** out);
+int cord_sls_destroy(cord_sls* sls);
+int cord_sls_kalman(cord_sls* sls, const float* A, const float* E, const float* F, const float* Xi, int32_t mode,
+                    float* Pi, float* L, int32_t* status, void* stream);
+int cord_sls_observer(cord_sls* sls, const float* A, const float* L, float* Phx, float* Phy, void* stream);
+int cord_sls_state_feedback(cord_sls* sls, const float* A, const float* Bm, const float* K, float* Pbx, float* Pbu,
+                            void* stream);
+int cord_sls_assemble(cord_sls* sls, const float* A, const float* Pbx, const float* Pbu, const float* Phx,
+                      const float* Phy, float* Pxw, float* Puw, float* Pxe, float* Pue, void* stream);
+int cord_sls_tubes(cord_sls* sls, const float* Pxw, const float* Pxe, const float* Puw, const float* Pue,
+                   const float* E, const float* F, float* tau_x, float* tau_u, void* stream);
+
 /* Thread-local message of the last error on this thread ("" if none). */
 const char* cord_last_error(void);
 

@@ -28,6 +28,7 @@ ROPE, CLOTH = 0, 1
 STORE_FULL, STORE_CKPT, STORE_FINAL = 0, 1, 2
 GRIP_DIRICHLET, GRIP_PENALTY = 0, 1
 LAUNCH_GROUPED, LAUNCH_PER_INSTANCE, LAUNCH_PERSISTENT, LAUNCH_GRAPH = 0, 1, 2, 3
+SLS_SERIAL, SLS_SCAN = 0, 1
 
 
 class Params(ctypes.Structure):
@@ -110,6 +111,13 @@ _EXPORTS = {
     "cord_plan_wait": (c_int32, [c_void_p, ctypes.c_uint64, c_int32, POINTER(PlanResult)]),
     "cord_plan_release": (c_int32, [c_void_p, ctypes.c_uint64]),
     "cord_server_stats": (c_int32, [c_void_p, POINTER(c_int64)]),
+    "cord_sls_create": (c_int32, [c_int32, c_int32, c_int32, c_int32, POINTER(c_void_p)]),
+    "cord_sls_destroy": (c_int32, [c_void_p]),
+    "cord_sls_kalman": (c_int32, [c_void_p] * 5 + [c_int32] + [c_void_p] * 4),
+    "cord_sls_observer": (c_int32, [c_void_p] * 6),
+    "cord_sls_state_feedback": (c_int32, [c_void_p] * 7),
+    "cord_sls_assemble": (c_int32, [c_void_p] * 11),
+    "cord_sls_tubes": (c_int32, [c_void_p] * 10),
 }
 
 _lib = None

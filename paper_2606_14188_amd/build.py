@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libcord.so")
 ROOT = os.path.dirname(HERE)
 
 SOURCES = ["cord_kernels.hip", "cord_cfg_rope.hip", "cord_cfg_cloth_a.hip", "cord_cfg_cloth_b.hip", "cord_cfg_cloth_c.hip",
-           "cord_lin_rope.hip", "cord_plan.hip", "cord_noalloc.hip", "cord_conformal.hip", "cord_api.cpp", "cord_server.cpp"]
+           "cord_lin_rope.hip", "cord_plan.hip", "cord_noalloc.hip", "cord_conformal.hip", "cord_sls.hip", "cord_api.cpp", "cord_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 BUILD_DIR = os.path.join(ROOT, "_build")
 

@@ -110,3 +110,25 @@ def test_null_arguments():
     assert lib.cord_linearize(None, None, None, None, None, None, None, None) == L.CORD_EINVAL
     assert lib.cord_sim_destroy(None) == 0
     assert lib.cord_last_error().decode()
+
+
+def test_sls_handle_validation():
+    """cord_sls_create rejects bad sizes before allocating; NULL handles and
+    buffers are rejected by every SLS call."""
+    L, lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.cord_sls_create(0, 10, 5, 2, ctypes.byref(h)) == L.CORD_EINVAL
+    assert lib.cord_sls_create(1, 0, 5, 2, ctypes.byref(h)) == L.CORD_EINVAL
+    assert lib.cord_sls_create(1, 10, 0, 2, ctypes.byref(h)) == L.CORD_EINVAL
+    assert lib.cord_sls_create(1, 10, 5, -1, ctypes.byref(h)) == L.CORD_EINVAL
+    assert lib.cord_sls_create(1, 10, 5, 2, None) == L.CORD_EINVAL
+    assert lib.cord_sls_create(1, 10, 2000, 2, ctypes.byref(h)) == L.CORD_EUNSUPPORTED
+    assert lib.cord_sls_create(64, 1000, 1000, 2, ctypes.byref(h)) == L.CORD_ETOOBIG
+    assert h.value is None
+    null = ctypes.c_void_p(0)
+    assert lib.cord_sls_kalman(null, *[null] * 4, 1, *[null] * 4) == L.CORD_EINVAL
+    assert lib.cord_sls_observer(*[null] * 6) == L.CORD_EINVAL
+    assert lib.cord_sls_state_feedback(*[null] * 7) == L.CORD_EINVAL
+    assert lib.cord_sls_assemble(*[null] * 11) == L.CORD_EINVAL
+    assert lib.cord_sls_tubes(*[null] * 10) == L.CORD_EINVAL
+    assert lib.cord_sls_destroy(null) == L.CORD_OK

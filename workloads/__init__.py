@@ -22,4 +22,5 @@ from .gen import (  # noqa: F401
     compressed_rope,
     calibration_set,
     lift_rope_envs,
+    sls_system,
 )

@@ -391,3 +391,28 @@ def serve_trace(rate: float = 200.0, duration: float = 60.0, seed: int = 1005, T
         out.append((t, inst, inst.n - 1, goal))
         k += 1
     return out
+
+
+def sls_system(B: int, N: int, n: int, m: int, seed: int = 1016, r: float = 0.05, rho: float = 0.1):
+    """Seeded inputs of the output-feedback SLS stage (float32, C = I): per
+    instance and step a linearization A_j = I + 0.15 G / sqrt(n) (spectral
+    radius near 1, like a time step of a damped mass-spring system), input
+    matrices B_j (n x m), disturbance scalings E_j = r (I + 0.2 G / sqrt(n))
+    and F_j = rho (I + 0.2 G / sqrt(n)), a state-feedback gain K_j (m x n,
+    j = 0 .. N) of scale 0.2 / sqrt(n), and Xi = 3 rho (I + 0.2 G / sqrt(n)),
+    with G standard normal.  Returns dict(A, E, F, Xi, Bm, K)."""
+    rng = np.random.default_rng(seed)
+    I = np.eye(n)
+    s = 1.0 / np.sqrt(n)
+
+    def near_identity(scale, lead):
+        return scale * (I + 0.2 * s * rng.normal(size=lead + (n, n)))
+
+    A = I + 0.15 * s * rng.normal(size=(B, N, n, n))
+    E = near_identity(r, (B, N))
+    F = near_identity(rho, (B, N))
+    Xi = near_identity(3 * rho, (B,))
+    Bm = s * rng.normal(size=(B, N, n, m))
+    K = -0.2 * s * rng.normal(size=(B, N + 1, m, n))
+    f32 = lambda x: np.ascontiguousarray(x, dtype=np.float32)  # noqa: E731
+    return dict(A=f32(A), E=f32(E), F=f32(F), Xi=f32(Xi), Bm=f32(Bm), K=f32(K))
