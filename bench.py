@@ -244,6 +244,82 @@ def bench_c4(args):
     return out
 
 
+def sls_tri_flops(N, n, ra_list):
+    """Algorithmic FLOPs of the assembly products C = A B with A block-lower
+    (row blocks of ra, column blocks of n) and B block-lower (n x n blocks):
+    output block (i, j), j <= i, sums i - j + 1 products of ra x n by n x n,
+    so 2 ra n^2 sum_i (i+1)(i+2)/2 per product."""
+    s = sum((i + 1) * (i + 2) // 2 for i in range(N + 1))
+    return float(sum(2.0 * ra * n * n * s for ra in ra_list))
+
+
+def bench_sls(args):
+    """Output-feedback SLS stage 3 on the A_t of 64 ropes of 13 nodes
+    (n_s = 78, the paper's output-feedback rope has 13 nodes) over N = 40
+    steps, C = I, E = r_CP I, F = rho I: the Kalman recursion serially and as
+    the associative scan (batch 64 and batch 1), the observer responses, the
+    state-feedback stand-in, the block-triangular assembly and the tubes."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2606_14188_amd import Sim
+    from paper_2606_14188_amd.sls import SCAN, SERIAL, SLS
+    B, nodes, N = 64, 13, 40
+    insts = W.small_rope_batch(B, nodes, N, seed=1019)
+    sim = Sim(insts)
+    s0 = sim.pack_states([i.s0 for i in insts])
+    u = sim.pack_controls([i.u for i in insts])
+    traj = sim.rollout(s0, u)
+    A, Bm, _ = sim.linearize(traj, u)
+    ns, m = insts[0].n_s, insts[0].n_u
+    A = A.reshape(B, N, ns, ns)
+    Bm = Bm.reshape(B, N, ns, m)
+    del sim, traj
+    eye = torch.eye(ns, device=A.device)
+    r_cp, rho = 1e-3, 2e-3
+    E = (r_cp * eye).expand(B, N, ns, ns).contiguous()
+    F = (rho * eye).expand(B, N, ns, ns).contiguous()
+    Xi = (rho * eye).expand(B, ns, ns).contiguous()
+    K = torch.from_numpy(W.sls_system(B, N, ns, m, seed=1020)["K"]).to(A.device)
+    h = SLS(B, N, ns, m)
+    h1 = SLS(1, N, ns, m)
+    reps = max(3, args.steps)
+    out = {"workload": f"SLS stage 3 on rope-{nodes} A_t (n_s={ns}, n_u={m}) x {B}, N={N}, C=I",
+           "B": B, "N": N, "n": ns, "m": m}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            res = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts)), res
+
+    ms = {}
+    ms["kalman_serial_b64"], _ = timed(lambda: h.kalman(A, E, F, Xi, mode=SERIAL))
+    ms["kalman_scan_b64"], (Pi, Lg, st) = timed(lambda: h.kalman(A, E, F, Xi, mode=SCAN))
+    A1, E1, F1, X1 = A[:1].contiguous(), E[:1].contiguous(), F[:1].contiguous(), Xi[:1].contiguous()
+    ms["kalman_serial_b1"], _ = timed(lambda: h1.kalman(A1, E1, F1, X1, mode=SERIAL))
+    ms["kalman_scan_b1"], _ = timed(lambda: h1.kalman(A1, E1, F1, X1, mode=SCAN))
+    ms["observer"], (Phx, Phy) = timed(lambda: h.observer(A, Lg))
+    ms["state_feedback"], (Pbx, Pbu) = timed(lambda: h.state_feedback(A, Bm, K))
+    ms["assemble"], (xw, uw, xe, ue) = timed(lambda: h.assemble(A, Pbx, Pbu, Phx, Phy))
+    ms["tubes"], (tx, tu) = timed(lambda: h.tubes(xw, xe, E, F, uw, ue))
+    out["ms"] = ms
+    out["status_nonzero"] = int((st.cpu().numpy() != 0).sum())
+    out["tau_x_final_max"] = float(tx[:, -1].max())
+    f = B * sls_tri_flops(N, ns, [ns, ns, m, m])
+    achieved = f / (ms["assemble"] / 1e3) / 1e12
+    out["assemble_roofline"] = {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                                "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "flops": f}
+    return out
+
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 PROFILE = os.path.join(HERE, "profiles", "rollout_backward_linearize__rope64x1024_T100.md")
 LIN_SOURCES = ["cord_lin_direct.h", "cord_solver.h", "cord_lin_rope.hip"]
@@ -410,7 +486,7 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes (default: host cores, at most 16)")
     ap.add_argument("--cpu-sample", type=int, default=32, help="oracle instances of the rope batch")
     ap.add_argument("--cpu-T", type=int, default=100)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "probe", "copy"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "probe", "copy", "sls"])
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=22.0,
                     help="length of the Poisson trace of the serving leg (the first 2 s are discarded)")
@@ -420,7 +496,7 @@ def main():
     ap.add_argument("--grasp", default="dirichlet", choices=["dirichlet", "penalty"],
                     help="grasp of the rope batch (penalty: holonomic penalty with smoothed activation)")
     ap.add_argument("--no-serve", action="store_true", help="skip the planning-stream leg")
-    ap.add_argument("--no-extras", action="store_true", help="skip the cloth (C3) and mixed-batch (C4) legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the cloth (C3), mixed-batch (C4) and SLS legs")
     ap.add_argument("--overlap", action="store_true",
                     help="run the adjoint and the linearization concurrently on two streams, both after "
                          "the rollout (default: one after the other on one stream, so that each kernel's "
@@ -443,6 +519,9 @@ def main():
         return bench_probe(args)
     if args.workload == "c5":
         print(json.dumps(bench_c5(args)), flush=True)
+        return
+    if args.workload == "sls":
+        print(json.dumps(bench_sls(args)), flush=True)
         return
 
     with_lin = not args.no_linearize
@@ -576,7 +655,7 @@ def main():
     # there is recorded instead of losing the line)
     if not args.no_extras:
         extras = {}
-        for name, fn in (("c3", bench_c3), ("c4", bench_c4)):
+        for name, fn in (("c3", bench_c3), ("c4", bench_c4), ("sls", bench_sls)):
             try:
                 extras[name] = fn(args)
             except Exception as e:      # noqa: BLE001

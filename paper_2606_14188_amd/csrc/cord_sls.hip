@@ -148,39 +148,39 @@ __device__ void wg_ident(float* dst, int ldd, int n) {
 // ---------------------------------------------------------------- workgroup solve
 // Gauss-Jordan with partial pivoting on G = [M | R] (n rows, ld = n + m):
 // on return G[:, n : n + m] = M^{-1} R.  Returns false if a pivot is zero or
-// not finite.  `red` is 2 * kThreads floats of LDS.
+// not finite.  `red` is 2 * kThreads floats of LDS.  Per column: the first
+// wavefront finds the pivot with shuffles (no barrier inside), then one
+// barrier each after the search, the row swap and the elimination.
 __device__ bool wg_solve(float* G, int ld, int n, int m, float* red) {
     const int tid = threadIdx.x;
     const int W = n + m;
+    int* pidx = reinterpret_cast<int*>(red);
     bool ok = true;
     for (int k = 0; k < n; ++k) {
-        // pivot: the largest |G[i][k]| for i >= k (lowest row on ties)
-        float best = -1.f;
-        int bi = k;
-        for (int i = k + tid; i < n; i += kThreads) {
-            const float a = fabsf(G[(size_t)i * ld + k]);
-            if (a > best) { best = a; bi = i; }
-        }
-        red[tid] = best;
-        reinterpret_cast<int*>(red)[kThreads + tid] = bi;
-        __syncthreads();
-        for (int s = kThreads / 2; s > 0; s >>= 1) {
-            if (tid < s) {
-                const float o = red[tid + s];
-                const int oi = reinterpret_cast<int*>(red)[kThreads + tid + s];
-                const int mi = reinterpret_cast<int*>(red)[kThreads + tid];
-                if (o > red[tid] || (o == red[tid] && oi < mi)) {
-                    red[tid] = o;
-                    reinterpret_cast<int*>(red)[kThreads + tid] = oi;
-                }
+        if (tid < 64) {
+            // the largest |G[i][k]| for i >= k, lowest row on ties
+            float best = -1.f, bv = 0.f;
+            int bi = n;
+            for (int i = k + tid; i < n; i += 64) {
+                const float v = G[(size_t)i * ld + k];
+                if (fabsf(v) > best) { best = fabsf(v); bv = v; bi = i; }
             }
-            __syncthreads();
+            for (int o = 32; o >= 1; o >>= 1) {
+                const float ob = __shfl_xor(best, o, 64);
+                const float ov = __shfl_xor(bv, o, 64);
+                const int oi = __shfl_xor(bi, o, 64);
+                if (ob > best || (ob == best && oi < bi)) { best = ob; bv = ov; bi = oi; }
+            }
+            if (tid == 0) {
+                pidx[0] = bi < n ? bi : k;
+                red[1] = bi < n ? bv : G[(size_t)k * ld + k];
+            }
         }
-        const int p = reinterpret_cast<int*>(red)[kThreads];
-        const float pv = G[(size_t)p * ld + k];
+        __syncthreads();
+        const int p = pidx[0];
+        const float pv = red[1];
         if (!(fabsf(pv) > 0.f) || !isfinite(pv)) ok = false;
         const float inv = 1.f / pv;
-        __syncthreads();
         // swap rows k and p and scale the new row k (columns k .. W-1)
         for (int c = k + tid; c < W; c += kThreads) {
             const float a = G[(size_t)k * ld + c];
@@ -189,15 +189,19 @@ __device__ bool wg_solve(float* G, int ld, int n, int m, float* red) {
             G[(size_t)k * ld + c] = b * inv;
         }
         __syncthreads();
-        // eliminate column k from every other row (columns k+1 .. W-1)
+        // eliminate column k from every other row (columns k+1 .. W-1); the
+        // flat index e = i wc + (c - k - 1) advances by kThreads per pass
         const int wc = W - k - 1;
-        if (wc > 0)
-            for (int e = tid; e < n * wc; e += kThreads) {
-                const int i = e / wc;
-                if (i == k) continue;
-                const int c = k + 1 + (e - i * wc);
-                G[(size_t)i * ld + c] -= G[(size_t)i * ld + k] * G[(size_t)k * ld + c];
+        if (wc > 0) {
+            int i = tid / wc, c = tid - i * wc;
+            const int di = kThreads / wc, dc = kThreads - di * wc;
+            for (; i < n;) {
+                if (i != k) G[(size_t)i * ld + k + 1 + c] -= G[(size_t)i * ld + k] * G[(size_t)k * ld + k + 1 + c];
+                i += di;
+                c += dc;
+                if (c >= wc) { c -= wc; ++i; }
             }
+        }
         __syncthreads();
     }
     return ok;
@@ -445,25 +449,30 @@ __global__ __launch_bounds__(kThreads) void trans_round_kernel(TArgs t, int d0, 
 }
 
 // ---------------------------------------------------------------- assembly
-// grid (N+1, B): block row i of M X = X - Z A X: (M X)_i = X_i - A_{i-1} X_{i-1}
-// for the dense block-lower X ((N+1) n x cols).
+// grid (N+1, column tiles of 64, B): block row i of M X = X - Z A X,
+// (M X)_i = X_i - A_{i-1} X_{i-1}, for the dense block-lower X ((N+1) n x cols).
 __global__ __launch_bounds__(kThreads) void shift_kernel(int N, int n, int cols, const float* A, const float* X,
                                                          float* out) {
     extern __shared__ float lds[];
-    const int i = blockIdx.x, b = blockIdx.y;
+    const int i = blockIdx.x, c0 = blockIdx.y * kTile, b = blockIdx.z;
     const size_t D = (size_t)(N + 1) * n;
+    const int cw = std::min(kTile, cols - c0);
     const float* Xb = X + (size_t)b * D * cols;
-    float* Ob = out + (size_t)b * D * cols;
+    float* Ob = out + (size_t)b * D * cols + (size_t)i * n * cols + c0;
     if (i == 0) {
-        wg_copy(Ob, cols, Xb, cols, n, cols, 1.f, 0.f);
+        wg_copy(Ob, cols, Xb + c0, cols, n, cw, 1.f, 0.f);
         return;
     }
-    // columns of block row i beyond the diagonal block are zero in both terms
-    const int w = std::min<int>(cols, (i + 1) * n);
-    wg_gemm(Ob + (size_t)i * n * cols, cols, A + ((size_t)b * N + i - 1) * n * n, n, false,
-            Xb + (size_t)(i - 1) * n * cols, cols, false, n, w, n, -1.f, Xb + (size_t)i * n * cols, cols, nullptr, 0,
-            0.f, lds);
-    if (w < cols) wg_zero(Ob + (size_t)i * n * cols + w, cols, n, cols - w);
+    // columns beyond the diagonal block of row i are zero in both terms
+    const int w = std::min<int>(cols, (i + 1) * n) - c0;
+    if (w <= 0) {
+        wg_zero(Ob, cols, n, cw);
+        return;
+    }
+    const int ww = std::min(w, cw);
+    wg_gemm(Ob, cols, A + ((size_t)b * N + i - 1) * n * n, n, false, Xb + (size_t)(i - 1) * n * cols + c0, cols,
+            false, n, ww, n, -1.f, Xb + (size_t)i * n * cols + c0, cols, nullptr, 0, 0.f, lds);
+    if (ww < cw) wg_zero(Ob + ww, cols, n, cw - ww);
 }
 
 // One output tile per workgroup of C = alpha A B + add1 + add2 with A
@@ -498,30 +507,50 @@ __global__ __launch_bounds__(kThreads) void tri_gemm_kernel(int rows, int cols, 
 }
 
 // ---------------------------------------------------------------- tubes
-// grid (N+1, B): tau_k[r] = sum_{j<k} |row r of Pw_{k,j+1} E_j| + |row r of Pe_{k,j+1} F_j|
-// for the dense Pw ((N+1) rr x D) and Pe ((N+1) rr x D).
-__global__ __launch_bounds__(kThreads) void tube_kernel(int N, int n, int rr, const float* Pw, const float* Pe,
-                                                        const float* E, const float* F, float* tau, float* ws,
-                                                        size_t ws_stride) {
+// grid (N, N+1, B), workgroup (j, k) with j < k: the row norms of
+// Pw_{k,j+1} E_j and of Pe_{k,j+1} F_j for the dense Pw, Pe ((N+1) rr x D),
+// their sum per row to part[b][k][j][:].  The products go through LDS in
+// 64 x 64 pieces; a thread owns one row of a 64-row piece and accumulates
+// its squares over the column pieces.
+__global__ __launch_bounds__(kThreads) void tube_part_kernel(int N, int n, int rr, const float* Pw, const float* Pe,
+                                                             const float* E, const float* F, float* part) {
     extern __shared__ float lds[];
-    const int k = blockIdx.x, b = blockIdx.y;
+    const int j = blockIdx.x, k = blockIdx.y, b = blockIdx.z;
+    if (j >= k) return;
     const size_t D = (size_t)(N + 1) * n;
-    float* P = ws + ((size_t)b * (N + 1) + k) * ws_stride;
-    float* out = tau + ((size_t)b * (N + 1) + k) * rr;
-    for (int r = threadIdx.x; r < rr; r += kThreads) out[r] = 0.f;
-    __syncthreads();
-    for (int j = 0; j < k; ++j) {
+    float* Pt = lds + kGemmLds;
+    float* out = part + (((size_t)b * (N + 1) + k) * N + j) * rr;
+    const int tid = threadIdx.x;
+    for (int r0 = 0; r0 < rr; r0 += kTile) {
+        const int rows = std::min(kTile, rr - r0);
+        float norm = 0.f;
         for (int s = 0; s < 2; ++s) {
-            const float* Ph = (s ? Pe : Pw) + (size_t)b * (N + 1) * rr * D + (size_t)k * rr * D + (size_t)(j + 1) * n;
+            const float* Ph = (s ? Pe : Pw) + (size_t)b * (N + 1) * rr * D + ((size_t)k * rr + r0) * D +
+                              (size_t)(j + 1) * n;
             const float* S = (s ? F : E) + ((size_t)b * N + j) * n * n;
-            wg_gemm(P, n, Ph, (int)D, false, S, n, false, rr, n, n, 1.f, nullptr, 0, nullptr, 0, 0.f, lds);
-            for (int r = threadIdx.x; r < rr; r += kThreads) {
-                float q = 0.f;
-                for (int c = 0; c < n; ++c) q += P[(size_t)r * n + c] * P[(size_t)r * n + c];
-                out[r] += sqrtf(q);
+            float sq = 0.f;
+            for (int c0 = 0; c0 < n; c0 += kTile) {
+                const int cols = std::min(kTile, n - c0);
+                wg_gemm(Pt, kTile, Ph, (int)D, false, S + c0, n, false, rows, cols, n, 1.f, nullptr, 0, nullptr, 0,
+                        0.f, lds);
+                if (tid < rows)
+                    for (int c = 0; c < cols; ++c) sq += Pt[tid * kTile + c] * Pt[tid * kTile + c];
+                __syncthreads();
             }
-            __syncthreads();
+            norm += sqrtf(sq);
         }
+        if (tid < rows) out[r0 + tid] = norm;
+    }
+}
+
+// grid (N+1, B): tau[b][k][r] = sum_{j<k} part[b][k][j][r], in increasing j.
+__global__ __launch_bounds__(kThreads) void tube_sum_kernel(int N, int rr, const float* part, float* tau) {
+    const int k = blockIdx.x, b = blockIdx.y;
+    const float* p = part + ((size_t)b * (N + 1) + k) * N * rr;
+    for (int r = threadIdx.x; r < rr; r += kThreads) {
+        float acc = 0.f;
+        for (int j = 0; j < k; ++j) acc += p[(size_t)j * rr + r];
+        tau[((size_t)b * (N + 1) + k) * rr + r] = acc;
     }
 }
 
@@ -543,6 +572,7 @@ struct cord_sls {
     float* Ahat = nullptr;
     float* MX = nullptr;       // M Phihat^x
     float* MY = nullptr;       // M Phihat^y
+    float* tube_part = nullptr; // (B, N+1, N, max(n, m)) row norms per (k, j)
 };
 
 namespace {
@@ -602,9 +632,7 @@ int cord_sls_create(int32_t batch, int32_t horizon, int32_t n, int32_t n_u, cord
     const size_t steps = (size_t)batch * horizon;
     const size_t elems = (size_t)batch * (horizon + 1);
     // a slot holds X / T2 (n^2) and the solve matrix when it is not in LDS (3 n^2)
-    // (and a tube product block, max(n, m) x n)
-    const size_t slot = std::max(nn + (solve_in_lds(n, 2 * n) ? 0 : 3 * nn), (size_t)std::max(n, n_u) * n);
-    s->ws_stride = (slot + 63) / 64 * 64;
+    s->ws_stride = (nn + (solve_in_lds(n, 2 * n) ? 0 : 3 * nn) + 63) / 64 * 64;
     s->ws_slots = elems;
     bool ok = hipMalloc(&s->Qw, 4 * steps * nn) == hipSuccess && hipMalloc(&s->Rv, 4 * steps * nn) == hipSuccess &&
               hipMalloc(&s->el[0], 4 * elems * 3 * nn) == hipSuccess &&
@@ -612,7 +640,8 @@ int cord_sls_create(int32_t batch, int32_t horizon, int32_t n, int32_t n_u, cord
               hipMalloc(&s->ws, 4 * s->ws_slots * s->ws_stride) == hipSuccess &&
               hipMalloc(&s->Ahat, 4 * steps * nn) == hipSuccess &&
               hipMalloc(&s->MX, 4 * (size_t)batch * D * D) == hipSuccess &&
-              hipMalloc(&s->MY, 4 * (size_t)batch * D * D) == hipSuccess;
+              hipMalloc(&s->MY, 4 * (size_t)batch * D * D) == hipSuccess &&
+              hipMalloc(&s->tube_part, 4 * elems * horizon * (size_t)std::max(n, n_u)) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         cord_sls_destroy(s);
@@ -624,7 +653,7 @@ int cord_sls_create(int32_t batch, int32_t horizon, int32_t n, int32_t n_u, cord
 
 int cord_sls_destroy(cord_sls* s) {
     if (!s) return CORD_OK;
-    for (float* p : {s->Qw, s->Rv, s->el[0], s->el[1], s->ws, s->Ahat, s->MX, s->MY})
+    for (float* p : {s->Qw, s->Rv, s->el[0], s->el[1], s->ws, s->Ahat, s->MX, s->MY, s->tube_part})
         if (p) (void)hipFree(p);
     delete s;
     return CORD_OK;
@@ -732,9 +761,10 @@ int cord_sls_assemble(cord_sls* s, const float* A, const float* Pbx, const float
     const int n = s->n, m = s->m;
     const int D = (s->N + 1) * n, Du = (s->N + 1) * m;
     const size_t lb = sizeof(float) * kGemmLds;
-    hipLaunchKernelGGL(shift_kernel, dim3(s->N + 1, s->B), dim3(kThreads), lb, st, s->N, n, D, A, Phx, s->MX);
+    const dim3 gs(s->N + 1, (D + kTile - 1) / kTile, s->B);
+    hipLaunchKernelGGL(shift_kernel, gs, dim3(kThreads), lb, st, s->N, n, D, A, Phx, s->MX);
     SLS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(shift_kernel, dim3(s->N + 1, s->B), dim3(kThreads), lb, st, s->N, n, D, A, Phy, s->MY);
+    hipLaunchKernelGGL(shift_kernel, gs, dim3(kThreads), lb, st, s->N, n, D, A, Phy, s->MY);
     SLS_HIP(hipGetLastError());
     const dim3 gx((D + kTile - 1) / kTile, (D + kTile - 1) / kTile, s->B);
     const dim3 gu((D + kTile - 1) / kTile, (Du + kTile - 1) / kTile, s->B);
@@ -761,13 +791,16 @@ int cord_sls_tubes(cord_sls* s, const float* Pxw, const float* Pxe, const float*
     if (!s || !Pxw || !Pxe || !E || !F || !tau_x || ((Puw || Pue || tau_u) && !(Puw && Pue && tau_u && s->m >= 1)))
         return sls_fail(CORD_EINVAL, "cord_sls_tubes: bad arguments");
     hipStream_t st = (hipStream_t)stream;
-    const size_t lb = sizeof(float) * kGemmLds;
-    hipLaunchKernelGGL(tube_kernel, dim3(s->N + 1, s->B), dim3(kThreads), lb, st, s->N, s->n, s->n, Pxw, Pxe, E, F,
-                       tau_x, s->ws, s->ws_stride);
-    SLS_HIP(hipGetLastError());
-    if (tau_u) {
-        hipLaunchKernelGGL(tube_kernel, dim3(s->N + 1, s->B), dim3(kThreads), lb, st, s->N, s->n, s->m, Puw, Pue, E, F,
-                           tau_u, s->ws, s->ws_stride);
+    const size_t lb = sizeof(float) * (kGemmLds + kTile * kTile);
+    for (int pass = 0; pass < (tau_u ? 2 : 1); ++pass) {
+        const int rr = pass ? s->m : s->n;
+        const float* Pw = pass ? Puw : Pxw;
+        const float* Pe = pass ? Pue : Pxe;
+        hipLaunchKernelGGL(tube_part_kernel, dim3(s->N, s->N + 1, s->B), dim3(kThreads), lb, st, s->N, s->n, rr, Pw,
+                           Pe, E, F, s->tube_part);
+        SLS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(tube_sum_kernel, dim3(s->N + 1, s->B), dim3(kThreads), 0, st, s->N, rr, s->tube_part,
+                           pass ? tau_u : tau_x);
         SLS_HIP(hipGetLastError());
     }
     return CORD_OK;
