@@ -29,6 +29,23 @@ right-hand side gains -(dD_k) Delta_j at node j:
   H dy = (M/dt^2) dxhat - sum_k e_j [dD_k (y_j - g+_k) - D_k dg+_k]
   K dx+ = J dy - sum_k e_j dD_k Delta_j,   dD_k = D'_k . (dx_j - dg_k)
 
+Friction (mu > 0, smoothed kappa > 0; the step's stage 2 is the
+central-path point of the friction-cone barrier, see oracle.step).  Per
+pair c at node p, with u = s_p + D_p (s = y* - x), y_n = phi_c + n.D_p,
+T = I - n n^T, tau = T u, Q = y_n^2 - mu^2 |tau|^2, a = y_n n - mu^2 tau,
+the force is lam_c = kappa a / Q and G = P D - sum_c lam_c = 0.  Its
+derivatives:
+  K_c  = -dlam/dD  = (kappa/Q) (2 a a^T / Q - (n n^T - mu^2 T))
+  Ly_c = dlam/dy*  = (kappa/Q) (A_y - a q_y^T / Q),
+     A_y = n (n + Hc D)^T + y_n Hc + mu^2 ((n.u) Hc + n (Hc u)^T - T),
+     q_y = 2 y_n (n + Hc D) + 2 mu^2 (n.u) Hc tau - 2 mu^2 tau
+  Lx_c = dlam/dx_p = (kappa/Q) (mu^2 T - 2 mu^2 a tau^T / Q)
+(Hc the SDF Hessian; dn = Hc dy*, d tau = -(n.u) dn - n (dn.u) + T du).
+Then K = P + sum K_c and K dx+ = (K - W + sum Ly_c) dy - W_fg db +
+sum Lx_c dx_p: the step now depends on x directly, through the tangential
+displacement.  With mu = 0 these blocks reduce to the frictionless ones
+(K_c = lam/gap n n^T, Ly_c = lam Hc - lam/gap n (n + Hc D)^T, Lx_c = 0).
+
 Every product above is a plain sparse matrix product; every inverse is a
 sparse LU solve.
 """
@@ -52,6 +69,36 @@ def _blockdiag(lay, pair_node, mats):
     rows = (base[:, None, None] + ii[None]).ravel()
     cols = (base[:, None, None] + jj[None]).ravel()
     return sp.coo_matrix((mats.ravel(), (rows, cols)), shape=(3 * nf, 3 * nf)).tocsr()
+
+
+def friction_blocks(r, x, mu, kappa):
+    """Per-pair 3x3 blocks K_c, Ly_c, Lx_c of the friction-cone stage 2 (see
+    the module docstring), from a solved step r and the positions x at the
+    start of the step."""
+    nc = len(r.pair_node)
+    Kc = np.zeros((nc, 3, 3))
+    Ly = np.zeros((nc, 3, 3))
+    Lx = np.zeros((nc, 3, 3))
+    I3 = np.eye(3)
+    for c in range(nc):
+        p = r.pair_node[c]
+        n = r.normal[c]
+        Hc = r.curv[c]
+        Dp = r.delta[p]
+        u = (r.y[p] - x[p]) + Dp
+        yn = r.phi[c] + n @ Dp
+        T = I3 - np.outer(n, n)
+        tau = T @ u
+        Q = yn * yn - mu * mu * (tau @ tau)
+        a = yn * n - mu * mu * tau
+        w = kappa / Q
+        nu = n @ u
+        Kc[c] = w * (2.0 * np.outer(a, a) / Q - (np.outer(n, n) - mu * mu * T))
+        Ay = np.outer(n, n + Hc @ Dp) + yn * Hc + mu * mu * (nu * Hc + np.outer(n, Hc @ u) - T)
+        qy = 2.0 * yn * (n + Hc @ Dp) + 2.0 * mu * mu * nu * (Hc @ tau) - 2.0 * mu * mu * tau
+        Ly[c] = w * (Ay - np.outer(a, qy) / Q)
+        Lx[c] = w * (mu * mu * T - 2.0 * mu * mu * np.outer(a, tau) / Q)
+    return Kc, Ly, Lx
 
 
 class StepDerivative:
@@ -80,7 +127,16 @@ class StepDerivative:
         dp = r.delta[r.pair_node]                                   # (nc, 3)
         hd = np.einsum("cij,cj->ci", r.curv, dp)                    # d^2 phi D_p
         self.Hlu = spla.splu(self.Hff)
-        if kappa > 0.0:
+        self.Lx = None
+        if r.mu > 0.0 and len(r.pair_node):
+            if not kappa > 0.0:
+                raise NotImplementedError("hard-contact derivatives with friction")
+            Kc, Ly, Lx = friction_blocks(r, self.x, r.mu, kappa)
+            self.K = (self.Hff + _blockdiag(lay, r.pair_node, Kc)).tocsc()
+            self.Klu = spla.splu(self.K)
+            self.J = (self.K - self.Wff + _blockdiag(lay, r.pair_node, Ly)).tocsr()
+            self.Lx = _blockdiag(lay, r.pair_node, Lx)
+        elif kappa > 0.0:
             w = kappa / r.gap ** 2
             self.R = _blockdiag(lay, r.pair_node, w[:, None, None] * r.normal[:, :, None] * hd[:, None, :])
             self.K = (self.Hff + N.T @ sp.diags(w) @ N).tocsc()
@@ -129,7 +185,9 @@ class StepDerivative:
                 rhs1[sl] -= np.outer(r.y[j] - P.gplus[k], dDk) - P.D[k] * dgp
                 pen2[sl] -= np.outer(r.delta[j], dDk)
         dy_f = self.Hlu.solve(rhs1)
-        if self.kappa > 0.0:
+        if self.Lx is not None:
+            dxn_f = self.Klu.solve(self.J @ dy_f - self.Wfg @ db[gi] + pen2 + self.Lx @ dx[fi])
+        elif self.kappa > 0.0:
             dxn_f = self.Klu.solve(self.J @ dy_f - self.Wfg @ db[gi] + pen2)
         else:
             top = -((self.Wff - self.C) @ dy_f + self.Wfg @ db[gi]) + pen2
@@ -167,10 +225,12 @@ class StepDerivative:
             for k, j in enumerate(inst.grip_nodes):
                 ubar[3 * k:3 * k + 3] += vb[3 * j:3 * j + 3]
         # stage 2
-        if self.kappa > 0.0:
+        if self.kappa > 0.0 or self.Lx is not None:
             z = self.Klu.solve(xnb_f)
             ybar_f = self.J.T @ z
             bbar[gi] -= self.Wfg.T @ z
+            if self.Lx is not None:
+                xbar[fi] += self.Lx.T @ z
             a2 = z
         else:
             nf = len(fi)

@@ -31,7 +31,22 @@ Solver"), with the readings stated below where the paper is silent.
    equality-constrained KKT system exactly.
 5. x+ = y* + D on free nodes, v+ = (x+ - x)/dt.
 
-Friction is zero (the friction cone reduces to the normal half-line).
+Friction (mu > 0, eq. contact-constraint with Anitescu's relaxation): each
+pair's constraint value is y_c = [phi_c + n_c . D_p ; t_c . (s_p + D_p)]
+with s = y* - x the stage-1 displacement, i.e. the normal row linearised at
+y* as in eq. (dynamics-second-stage) and the tangential rows measuring the
+node's whole displacement over the step, x+_p - x_p, as in eq.
+(contact-constraint).  (Measured from y*, as the stage-2 equation prints
+it, the tangential rows would vanish at D = 0 and a projection onto the
+cone could never move a node tangentially: friction would do nothing.)
+The cone is F_mu = {lam : |lam_t| <= mu lam_n}, its dual F_mu^* =
+{y : y_n >= mu |y_t|}.  Smoothed (kappa > 0): the central-path point of
+min 1/2 D^T P D - kappa sum_c psi(y_c), psi(y) = 1/2 log(y_n^2 - mu^2
+|y_t|^2), whose stationarity gives lam_c = kappa grad psi(y_c) in F_mu,
+y_c in F_mu^* and y_c . lam_c = kappa, the paper's smoothed
+complementarity.  Hard (kappa = 0): the same problem followed along a
+decreasing kappa to 1e-16 fscale h.  With mu = 0 both reduce to the
+frictionless problem above.
 """
 from __future__ import annotations
 
@@ -67,6 +82,8 @@ class StepResult:
     extra: dict = field(default_factory=dict)
     g: np.ndarray = None   # (n_g, 3) next gripper positions (penalty mode)
     pen: object = None     # Penalty data of the step (penalty mode)
+    force: np.ndarray = None   # (nc, 3) contact forces with friction (mu > 0)
+    mu: float = 0.0
 
 
 @dataclass
@@ -315,6 +332,124 @@ def hard_crossover(P, N, phi, D, lam, gap, fscale, xscale):
     return D2, lam2, gap2, act, ok
 
 
+def tangent_basis(nrm):
+    """Unit vectors t1, t2 completing each normal to an orthonormal frame
+    (any choice: the cone and its barrier are invariant under rotations
+    about n)."""
+    a = np.where(np.abs(nrm[:, :1]) < 0.9, np.array([[1.0, 0.0, 0.0]]), np.array([[0.0, 1.0, 0.0]]))
+    t1 = np.cross(nrm, a)
+    t1 /= np.linalg.norm(t1, axis=1, keepdims=True)
+    return t1, np.cross(nrm, t1)
+
+
+def cone_barrier(y, mu):
+    """psi(y) = 1/2 log(y0^2 - mu^2 (y1^2 + y2^2)) per row of y (nc, 3):
+    gradient (nc, 3) and Hessian (nc, 3, 3)."""
+    w = np.array([1.0, -mu * mu, -mu * mu])
+    Q = y[:, 0] ** 2 - mu * mu * (y[:, 1] ** 2 + y[:, 2] ** 2)
+    gr = w[None] * y / Q[:, None]
+    H = np.diag(w)[None] / Q[:, None, None] - 2.0 * gr[:, :, None] * gr[:, None, :]
+    return gr, H
+
+
+def in_cone(y, mu):
+    return np.all(y[:, 0] > 0.0) and np.all(y[:, 0] ** 2 - mu * mu * (y[:, 1] ** 2 + y[:, 2] ** 2) > 0.0)
+
+
+def friction_barrier_point(P, J, b, kappa, mu, fscale, xscale, D0=None, y0=None, max_iter=200):
+    """Minimiser of 1/2 D^T P D - kappa sum_c psi(y_c) subject to y = J D + b
+    (J: 3 rows per pair, b (nc, 3)), by Newton's method from an infeasible
+    start on (D, y) with lam = kappa grad psi(y): residuals
+    r_D = P D - J^T lam and r_p = y - J D - b; the step solves
+    (P + J^T Hb J) dD = -r_D + J^T Hb r_p, dy = J dD - r_p with
+    Hb = -kappa Hess psi (positive semidefinite), then halves until y stays
+    inside the cone and the scaled residual decreases."""
+    nc = b.shape[0]
+    D = np.zeros(P.shape[0]) if D0 is None else D0.copy()
+    y = y0.copy()
+    JT = J.T.tocsr()
+
+    def resid(D, y):
+        gr, _ = cone_barrier(y, mu)
+        lam = kappa * gr
+        rD = P @ D - JT @ lam.ravel()
+        rp = (y.ravel() - J @ D - b.ravel())
+        return rD, rp, lam
+
+    rD, rp, lam = resid(D, y)
+    for it in range(max_iter):
+        nrm = np.sqrt(np.sum((rD / fscale) ** 2) + np.sum((rp / xscale) ** 2))
+        # the force balance is met to the rounding of the barrier gradient,
+        # whose value kappa / (y_n - mu |y_t|) cancels near the cone's surface
+        if (np.max(np.abs(rD)) <= 1e-13 * fscale + 1e-9 * np.max(np.abs(lam))
+                and np.max(np.abs(rp)) <= 1e-13 * xscale):
+            return D, y, lam, it, True
+        _, Hs = cone_barrier(y, mu)
+        Hb = -kappa * Hs
+        Hbd = sp.block_diag(list(Hb), format="csr")
+        K = (P + JT @ Hbd @ J).tocsc()
+        dD = spla.spsolve(K, -rD + JT @ (Hbd @ rp))
+        dy = (J @ dD - rp).reshape(nc, 3)
+        alpha = 1.0
+        for _ in range(80):
+            yn = y + alpha * dy
+            if in_cone(yn, mu):
+                rD2, rp2, lam2 = resid(D + alpha * dD, yn)
+                n2 = np.sqrt(np.sum((rD2 / fscale) ** 2) + np.sum((rp2 / xscale) ** 2))
+                if n2 <= (1.0 - 0.01 * alpha) * nrm:
+                    break
+            alpha *= 0.5
+        else:
+            return D, y, lam, it, False
+        D, y, rD, rp, lam = D + alpha * dD, yn, rD2, rp2, lam2
+    return D, y, lam, max_iter, False
+
+
+def friction_stage2(P, lay, pn, phi, nrm, s, mu, kappa, fscale, xscale):
+    """Stage 2 with the friction cone (see the module docstring).  Returns
+    D (free DoFs), y (nc, 3) in each pair's frame (n, t1, t2), the contact
+    forces lam (nc, 3) in world coordinates, iterations and success."""
+    nc = len(phi)
+    t1, t2 = tangent_basis(nrm)
+    frame = np.stack([nrm, t1, t2], axis=1)                      # (nc, 3, 3), rows n, t1, t2
+    rows = np.repeat(np.arange(3 * nc), 3)
+    cols = np.tile((3 * lay.fpos[pn][:, None] + np.arange(3)[None]), (1, 3)).ravel()
+    J = sp.csr_matrix((frame.reshape(nc, 9).ravel(), (rows, cols)), shape=(3 * nc, P.shape[0]))
+    b = np.stack([phi, np.einsum("ci,ci->c", t1, s), np.einsum("ci,ci->c", t2, s)], axis=1)
+    pii = np.asarray((J[0::3] @ P).multiply(J[0::3]).sum(axis=1)).ravel()
+    hard = kappa <= 0.0
+    k0 = kappa if not hard else max(1e-2 * float(np.mean(pii * phi ** 2)), 1e-12 * fscale * xscale)
+    # a strictly interior start: the current tangential displacement, a normal
+    # value above the cone by the relaxation's own gap scale
+    yt = b[:, 1:]
+    y = np.concatenate([(np.maximum(phi, 0.0) + mu * np.linalg.norm(yt, axis=1)
+                         + np.sqrt(k0 / pii))[:, None], yt], axis=1)
+    D = np.zeros(P.shape[0])
+    its = 0
+    kk = k0
+    last = None
+    while True:
+        D1, y1, lam1, it, ok = friction_barrier_point(P, J, b, kk, mu, fscale, xscale, D, y)
+        its += it
+        if not ok:
+            # a level below the first that does not converge ends the path
+            # at the previous one
+            if last is not None:
+                D, y, lam = last
+                ok = True
+            break
+        D, y, lam = D1, y1, lam1
+        last = (D, y, lam)
+        if not hard or kk <= 1e-16 * fscale * xscale:
+            break
+        kk = max(0.05 * kk, 1e-16 * fscale * xscale)
+        # move the slack back inside the cone for the smaller relaxation
+        y = np.concatenate([np.maximum(y[:, :1], mu * np.linalg.norm(y[:, 1:], axis=1, keepdims=True)
+                                       + 1e-3 * np.sqrt(kk / pii)[:, None]), y[:, 1:]], axis=1)
+    lam_w = np.einsum("ci,cij->cj", lam, frame)
+    return D, y, lam_w, its, ok
+
+
 def step(inst, x, v, u_t, kappa, el=None, lay=None, g=None) -> StepResult:
     """q+ = f(q, u) with contact relaxation kappa (kappa = 0: hard contact).
     Penalty mode needs the gripper positions g (n_g, 3)."""
@@ -354,7 +489,20 @@ def step(inst, x, v, u_t, kappa, el=None, lay=None, g=None) -> StepResult:
     it2 = 0
     if P.shape[0] and singular(P):
         status = max(status, STATUS_NOT_PD)
-    if len(phi):
+    mu = float(getattr(inst, "mu", 0.0))
+    force = None
+    if len(phi) and mu > 0.0:
+        s = (y - x)[pn]
+        D, yc, force, it2, ok = friction_stage2(P, lay, pn, phi, nrm, s, mu, kappa, fscale, xscale)
+        lam = np.einsum("ci,ci->c", force, nrm)
+        gap = yc[:, 0]
+        active = np.zeros(len(phi), dtype=bool)
+        if not ok:
+            status = max(status, STATUS_QP_NOCONV)
+        full = np.zeros(3 * inst.n)
+        full[lay.fidx] = D
+        delta = full.reshape(inst.n, 3)
+    elif len(phi):
         N = normal_matrix(lay, pn, nrm)
         D, lam, gap, it2, ok = interior_point(P, N, phi, kappa, fscale, xscale)
         if kappa <= 0.0:
@@ -375,7 +523,8 @@ def step(inst, x, v, u_t, kappa, el=None, lay=None, g=None) -> StepResult:
     if not (np.all(np.isfinite(xn)) and np.all(np.isfinite(vn))):
         status = STATUS_NONFINITE
     return StepResult(xn, vn, y, delta, xhat, pn, po, phi, nrm, curv, lam, gap, active,
-                      kappa, status, it1, it2, g=None if pen is None else pen.gplus, pen=pen)
+                      kappa, status, it1, it2, g=None if pen is None else pen.gplus, pen=pen,
+                      force=force, mu=mu)
 
 
 def split_state(inst, s):

@@ -60,6 +60,7 @@ class Instance:
     D_max: float = 0.0        # [N/m]
     kappa_h: float = 0.0      # [m]
     r_g: float = 0.0          # [m]
+    mu: float = 0.0           # friction coefficient of every contact (0: frictionless)
 
     @property
     def n(self) -> int:
