@@ -72,7 +72,7 @@ extern "C" {
 #define CORD_EINVAL        1   /* invalid argument or descriptor            */
 #define CORD_ENOMEM        2   /* device or host allocation failed          */
 #define CORD_EHIP          3   /* a HIP runtime call failed (see message)   */
-#define CORD_EUNSUPPORTED  4   /* valid but not supported (e.g. mu != 0)    */
+#define CORD_EUNSUPPORTED  4   /* valid but not supported (e.g. too many obstacles) */
 #define CORD_EAGAIN        5   /* queue full, try again                     */
 #define CORD_ETOOBIG       6   /* request larger than the memory budget     */
 
@@ -102,11 +102,18 @@ extern "C" {
  *             gamma = 1 is the paper's quasi-static eq. (dynamics).
  *   gravity   [m/s^2], part of tau(u) in eq. (dynamics)
  *   kappa_fwd contact relaxation of rollouts [J]; 0 = hard contact
- *             (eq. contact-constraint with mu = 0)
+ *             (eq. contact-constraint)
  *   kappa_bwd contact relaxation of the derivatives [J], > 0.  kappa_fwd = 0
  *             < kappa_bwd is the paper's surrogate-gradient mode.
- *   mu        friction coefficient of the cone F_mu; must be 0
- *             (otherwise CORD_EUNSUPPORTED).
+ *   mu        friction coefficient of the cone F_mu = {lam : |lam_t| <=
+ *             mu lam_n} of eq. (contact-constraint), >= 0.  With mu > 0 the
+ *             constraint value of a contact pair is [phi + n.D ; the
+ *             tangential part of the node's displacement over the step],
+ *             held in the dual cone {y_n >= mu |y_t|} (Anitescu's
+ *             relaxation); smoothed it is the central point y . lam = kappa
+ *             of the cone's barrier.  Friction needs kappa_fwd > 0
+ *             (otherwise CORD_EUNSUPPORTED).  Dense A_t/B_t of such
+ *             instances use the row-by-row kernel.
  */
 typedef struct {
     float dt;
@@ -170,8 +177,9 @@ typedef struct cord_sim cord_sim;
  * current HIP device.
  * Errors: CORD_EINVAL (n_inst < 1, dt <= 0, gamma outside [0,1], rope with
  * ny != 1, cloth with nx or ny < 2, n < 1, bad grip/obstacle data, T < 1,
- * kappa_bwd <= 0 or kappa_fwd < 0, mass <= 0, h <= 0, negative stiffness),
- * CORD_EUNSUPPORTED (mu != 0, more than CORD_MAX_OBST obstacles, a node
+ * kappa_bwd <= 0 or kappa_fwd < 0, mass <= 0, h <= 0, negative stiffness,
+ * mu < 0 or not finite),
+ * CORD_EUNSUPPORTED (mu > 0 with kappa_fwd = 0, more than CORD_MAX_OBST obstacles, a node
  * count no kernel configuration covers: ropes up to 256 nodes, cloths up
  * to 2304 nodes), CORD_ENOMEM, CORD_EHIP.  *out is set only on success.
  */

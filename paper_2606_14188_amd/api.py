@@ -56,7 +56,7 @@ def make_desc(inst) -> L.InstanceDesc:
     p.dt, p.gamma = float(inst.dt), float(inst.gamma)
     for c in range(3):
         p.gravity[c] = float(inst.gravity[c])
-    p.kappa_fwd, p.kappa_bwd, p.mu = float(inst.kappa_fwd), float(inst.kappa_bwd), 0.0
+    p.kappa_fwd, p.kappa_bwd, p.mu = float(inst.kappa_fwd), float(inst.kappa_bwd), float(getattr(inst, "mu", 0.0))
     if getattr(inst, "grip_mode", "dirichlet") == "penalty":
         d.grip_mode = L.GRIP_PENALTY
         d.D_max, d.kappa_h, d.r_g = float(inst.D_max), float(inst.kappa_h), float(inst.r_g)

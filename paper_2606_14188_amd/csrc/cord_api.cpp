@@ -54,7 +54,7 @@ const int kRopeBuckets[] = {32, 64, 128, 256};
 const int kClothBuckets[] = {64, 128, 256, 512, 1024, 2304};
 
 // Dense A_t/B_t of rope classes go to the banded direct kernel; JVPs, cloth,
-// B_t alone, penalty grasps and classes it does not cover use the class's
+// B_t alone, penalty grasps, friction and classes it does not cover use the class's
 // iterative kernel.
 // Setting CORD_LINEARIZE_ITERATIVE=1 in the environment forces the iterative
 // kernel everywhere (for comparisons).
@@ -68,12 +68,13 @@ bool use_iterative_only() {
 }
 }  // namespace
 
-hipError_t launch_linearize(int cfg_index, int topo, int nmax, bool penalty, const KArgs& a, int nblk, int tmax,
-                            hipStream_t st, const KeptSource& ks) {
+hipError_t launch_linearize(int cfg_index, int topo, int nmax, bool penalty, bool fric, const KArgs& a, int nblk,
+                            int tmax, hipStream_t st, const KeptSource& ks) {
     int count = 0;
     const KernelCfg* cfg = kernel_configs(&count);
+    const auto lin = fric ? cfg[cfg_index].linearize_f : cfg[cfg_index].linearize;
     int wg = 0;
-    const size_t kf = (a.A && topo == kRope && !penalty && !use_iterative_only())
+    const size_t kf = (a.A && topo == kRope && !penalty && !fric && !use_iterative_only())
                           ? linearize_rope_direct_scratch(nmax, &wg) : 0;
     if (wg > 0) {
         KArgs ad = a;
@@ -91,17 +92,17 @@ hipError_t launch_linearize(int cfg_index, int topo, int nmax, bool penalty, con
             // other workgroups of this launch return at once
             KArgs ar = a;
             ar.jvp_k = 0; ar.jvp_ds = nullptr; ar.jvp_du = nullptr; ar.jvp_out = nullptr;
-            e = cfg[cfg_index].linearize(ar, nblk, tmax, st);
+            e = lin(ar, nblk, tmax, st);
             if (e != hipSuccess) return e;
         }
         if (!a.jvp_out) return hipSuccess;
         KArgs aj = a;
         aj.A = nullptr; aj.Bm = nullptr; aj.redo = nullptr;
-        return cfg[cfg_index].linearize(aj, nblk, tmax, st);
+        return lin(aj, nblk, tmax, st);
     }
     KArgs ai = a;
     ai.redo = nullptr;
-    return cfg[cfg_index].linearize(ai, nblk, tmax, st);
+    return lin(ai, nblk, tmax, st);
 }
 
 int bucket_of(int topo, int n) {
@@ -124,6 +125,7 @@ struct Group {
     int tmax = 0;
     int cap[2] = {1, 1};       // persistent grid: resident workgroups (rollout, backward)
     bool penalty = false;      // some instance uses the penalty grasp
+    bool fric = false;         // some instance has friction (mu > 0): the friction kernels
 };
 
 enum Op { kOpRollout = 0, kOpBackward = 1 };
@@ -180,7 +182,9 @@ int validate(const cord_instance_desc& d, int i) {
     if (!(d.k_struct >= 0.f) || !(d.k_shear >= 0.f) || !(d.k_bend >= 0.f)) return fail(CORD_EINVAL, "instance %d: negative stiffness", i);
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(p.gravity[c])) return fail(CORD_EINVAL, "instance %d: gravity not finite", i);
-    if (p.mu != 0.f) return fail(CORD_EUNSUPPORTED, "instance %d: friction mu != 0 is not supported", i);
+    if (!(p.mu >= 0.f) || !std::isfinite(p.mu)) return fail(CORD_EINVAL, "instance %d: friction mu must be >= 0", i);
+    if (p.mu > 0.f && !(p.kappa_fwd > 0.f))
+        return fail(CORD_EUNSUPPORTED, "instance %d: friction (mu > 0) needs smoothed forward contact (kappa_fwd > 0)", i);
     const int n = d.nx * d.ny;
     if (d.n_grip < 0 || d.n_grip > CORD_MAX_GRIP) return fail(CORD_EINVAL, "instance %d: n_grip out of range", i);
     for (int g = 0; g < d.n_grip; ++g) {
@@ -220,6 +224,7 @@ void fill_instdev(const cord_instance_desc& d, InstDev& I) {
     I.grip_mode = d.grip_mode == CORD_GRIP_PENALTY ? 1 : 0;
     I.n_s = 6 * I.n + (I.grip_mode ? 3 * d.n_grip : 0); I.n_u = 3 * d.n_grip;
     I.D_max = d.D_max; I.kappa_h = d.kappa_h; I.r_g = d.r_g;
+    I.mu = d.params.mu;
     for (int g = 0; g < d.n_grip; ++g) I.grip_node[g] = d.grip_node[g];
     int o = 0;
     if (d.ground) { I.obs_type[o] = kObsGround; ++o; }
@@ -360,7 +365,8 @@ KArgs base_args(const cord_sim* s) {
     return a;
 }
 
-hipError_t launch_op(const KernelCfg& c, int op, const KArgs& a, int nblk, hipStream_t st) {
+hipError_t launch_op(const KernelCfg& c, int op, const KArgs& a, int nblk, hipStream_t st, bool fric) {
+    if (fric) return op == kOpRollout ? c.rollout_f(a, nblk, st) : c.backward_f(a, nblk, st);
     return op == kOpRollout ? c.rollout(a, nblk, st) : c.backward(a, nblk, st);
 }
 
@@ -379,7 +385,7 @@ int enqueue_persistent(cord_sim* s, int op, KArgs a, hipStream_t st) {
         a.ids = G.d_ids;
         a.n_ids = (int)G.ids.size();
         a.queue = s->d_queues + g;
-        CORD_HIP(launch_op(cfg[G.cfg], op, a, G.cap[op], sg));
+        CORD_HIP(launch_op(cfg[G.cfg], op, a, G.cap[op], sg, G.fric));
         CORD_HIP(hipEventRecord(s->join_ev[g], sg));
         CORD_HIP(hipStreamWaitEvent(st, s->join_ev[g], 0));
     }
@@ -403,7 +409,8 @@ int launch_all(cord_sim* s, int op, KArgs a, hipStream_t st) {
                 a.ids = s->d_ident + i;
                 a.n_ids = 1;
                 a.queue = nullptr;
-                CORD_HIP(launch_op(cfg[s->groups[s->group_of[i]].cfg], op, a, 1, st));
+                const Group& Gi = s->groups[s->group_of[i]];
+                CORD_HIP(launch_op(cfg[Gi.cfg], op, a, 1, st, Gi.fric));
             }
             return CORD_OK;
         }
@@ -446,7 +453,7 @@ int launch_all(cord_sim* s, int op, KArgs a, hipStream_t st) {
                 a.ids = G.d_ids;
                 a.n_ids = (int)G.ids.size();
                 a.queue = nullptr;
-                CORD_HIP(launch_op(cfg[G.cfg], op, a, a.n_ids, st));
+                CORD_HIP(launch_op(cfg[G.cfg], op, a, a.n_ids, st, G.fric));
             }
             return CORD_OK;
         }
@@ -563,6 +570,7 @@ int cord_sim_create(const cord_instance_desc* inst, int32_t n_inst, cord_sim** o
         const int gi = class_group[key];
         s->groups[gi].ids.push_back(i);
         if (I.grip_mode) s->groups[gi].penalty = true;
+        if (I.mu > 0.f) s->groups[gi].fric = true;
         s->groups[gi].tmax = std::max(s->groups[gi].tmax, I.T);
         s->group_of[i] = gi;
     }
@@ -778,7 +786,7 @@ int cord_rollout_backward_noalloc(cord_sim* s, const float* u, const float* traj
         a.ids = G.d_ids;
         a.n_ids = (int)G.ids.size();
         a.queue = nullptr;
-        CORD_HIP(launch_op(cfg[G.cfg], kOpBackward, a, a.n_ids, st));
+        CORD_HIP(launch_op(cfg[G.cfg], kOpBackward, a, a.n_ids, st, G.fric));
     }
     return CORD_OK;
 }
@@ -820,7 +828,8 @@ int cord_linearize(cord_sim* s, const float* traj, const float* u, float* A, flo
     for (const Group& g : s->groups) {
         a.ids = g.d_ids;
         a.n_ids = (int)g.ids.size();
-        CORD_HIP(launch_linearize(g.cfg, g.topo, g.nmax, g.penalty, a, a.n_ids, g.tmax, st, KeptSource{&sim_kept, s}));
+        CORD_HIP(launch_linearize(g.cfg, g.topo, g.nmax, g.penalty, g.fric, a, a.n_ids, g.tmax, st,
+                                  KeptSource{&sim_kept, s}));
     }
     return CORD_OK;
 }
@@ -911,7 +920,10 @@ int cord_autotune(cord_sim* s, const float* s0, const float* u, int32_t sample, 
                 std::vector<float> t;
                 for (int r = 0; r < 4; ++r) {
                     (void)hipEventRecord(e0, st);
-                    if (cfg[c].rollout(a, ns, st) != hipSuccess) { rc = fail(CORD_EHIP, "autotune launch"); break; }
+                    if ((G.fric ? cfg[c].rollout_f : cfg[c].rollout)(a, ns, st) != hipSuccess) {
+                        rc = fail(CORD_EHIP, "autotune launch");
+                        break;
+                    }
                     (void)hipEventRecord(e1, st);
                     (void)hipEventSynchronize(e1);
                     float ms = 0.f;

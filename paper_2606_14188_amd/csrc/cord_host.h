@@ -18,6 +18,9 @@ struct KeptSource {
     float* (*get)(void* ctx, size_t floats);
     void* ctx;
 };
-hipError_t launch_linearize(int cfg_index, int topo, int nmax, bool penalty, const KArgs& a, int nblk, int tmax,
-                            hipStream_t st, const KeptSource& ks);
+// penalty / fric: some instance of the launch uses the penalty grasp / has
+// friction (mu > 0); either rules out the banded direct kernel, and fric
+// selects the kernels compiled with the friction cone.
+hipError_t launch_linearize(int cfg_index, int topo, int nmax, bool penalty, bool fric, const KArgs& a, int nblk,
+                            int tmax, hipStream_t st, const KeptSource& ks);
 }  // namespace cord

@@ -26,7 +26,7 @@ struct alignas(16) InstDev {
     float h, mass, k_struct, k_shear;
     float k_bend, dt, gamma, kappa_fwd;
     float kappa_bwd, g0, g1, g2;
-    float D_max, kappa_h, r_g, pad3;
+    float D_max, kappa_h, r_g, mu;   // mu: friction coefficient (0: frictionless)
     int64_t s_off;      // sum n_s
     int64_t u_off;      // sum T n_u
     int64_t traj_off;   // sum (T+1) n_s

@@ -17,6 +17,10 @@ struct KernelCfg {
     hipError_t (*backward)(const KArgs&, int nblk, hipStream_t);
     hipError_t (*linearize)(const KArgs&, int nblk, int tmax, hipStream_t);
     int (*blocks_per_cu)(int which);   // occupancy of the rollout (0) / backward (1) kernel
+    // the same three kernels compiled with the friction cone (mu > 0)
+    hipError_t (*rollout_f)(const KArgs&, int nblk, hipStream_t);
+    hipError_t (*backward_f)(const KArgs&, int nblk, hipStream_t);
+    hipError_t (*linearize_f)(const KArgs&, int nblk, int tmax, hipStream_t);
 };
 
 const KernelCfg* kernel_configs(int* count);

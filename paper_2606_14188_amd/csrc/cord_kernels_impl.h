@@ -21,14 +21,14 @@ __device__ __forceinline__ int next_item(const KArgs& a, int prev, int* slot) {
     return *slot;
 }
 
-template <int TOPO, int NT, int PPT, int NOBS>
+template <int TOPO, int NT, int PPT, int NOBS, bool FRIC = false>
 __global__ __launch_bounds__(NT) void rollout_kernel(KArgs a) {
     extern __shared__ float lds[];
     __shared__ int slot;
     for (int w = next_item(a, -1, &slot); w < a.n_ids; w = next_item(a, w, &slot)) {
         const int id = a.ids[w];
         const InstDev& I = a.inst[id];
-        Solver<TOPO, NT, PPT, NOBS> S;
+        Solver<TOPO, NT, PPT, NOBS, true, FRIC> S;
         S.init(I, lds);
         S.load_state(a.s0 + I.s_off);
         const float kappa = a.use_kappa_bwd ? I.kappa_bwd : I.kappa_fwd;
@@ -72,8 +72,8 @@ __device__ __forceinline__ void add_cot(float xb[PPT][3], float vb[PPT][3], cons
 
 // Re-solve step t at kappa_bwd from the loaded state, apply its VJP, write
 // u_bar[t] and add the state cotangent of traj_bar[t].
-template <int TOPO, int NT, int PPT, int NOBS>
-__device__ __forceinline__ void adjoint_step(Solver<TOPO, NT, PPT, NOBS>& S, const KArgs& a, const InstDev& I, int t,
+template <int TOPO, int NT, int PPT, int NOBS, bool FRIC>
+__device__ __forceinline__ void adjoint_step(Solver<TOPO, NT, PPT, NOBS, true, FRIC>& S, const KArgs& a, const InstDev& I, int t,
                                              float xb[PPT][3], float vb[PPT][3], float ub[PPT][3]) {
     const int nu = I.n_u;
     if (a.aux_mode == 2 && I.kappa_fwd == I.kappa_bwd && a.store == CORD_STORE_FULL)
@@ -94,14 +94,14 @@ __device__ __forceinline__ void adjoint_step(Solver<TOPO, NT, PPT, NOBS>& S, con
     }
 }
 
-template <int TOPO, int NT, int PPT, int NOBS>
+template <int TOPO, int NT, int PPT, int NOBS, bool FRIC = false>
 __global__ __launch_bounds__(NT) void backward_kernel(KArgs a) {
     extern __shared__ float lds[];
     __shared__ int slot;
     for (int w = next_item(a, -1, &slot); w < a.n_ids; w = next_item(a, w, &slot)) {
         const int id = a.ids[w];
         const InstDev& I = a.inst[id];
-        Solver<TOPO, NT, PPT, NOBS> S;
+        Solver<TOPO, NT, PPT, NOBS, true, FRIC> S;
         S.init(I, lds);
         const int T = I.T, ns = I.n_s, nu = I.n_u, n = I.n, K = a.ckpt_every;
         const float kf = a.use_kappa_bwd ? I.kappa_bwd : I.kappa_fwd;
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(NT) void backward_kernel(KArgs a) {
 // One workgroup per (instance, step).  Dense rows of A_t/B_t come from one
 // VJP per free DoF row (rows written coalesced); JVP tangents from the
 // forward tangent map.
-template <int TOPO, int NT, int PPT, int NOBS>
+template <int TOPO, int NT, int PPT, int NOBS, bool FRIC = false>
 __global__ __launch_bounds__(NT) void linearize_kernel(KArgs a) {
     extern __shared__ float lds[];
     const int id = a.ids[blockIdx.x];
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(NT) void linearize_kernel(KArgs a) {
     const int t = blockIdx.y;
     if (t >= I.T) return;
     if (a.redo && !a.redo[I.t_off + t]) return;   // only the steps the direct kernel flagged
-    Solver<TOPO, NT, PPT, NOBS> S;
+    Solver<TOPO, NT, PPT, NOBS, true, FRIC> S;
     S.init(I, lds);
     const int n = I.n, ns = I.n_s, nu = I.n_u;
     const float kb = I.kappa_bwd, dt = I.dt, idt = 1.0f / I.dt;
@@ -324,6 +324,19 @@ struct Launch {
         hipLaunchKernelGGL((linearize_kernel<TOPO, NT, PPT, NOBS>), dim3(nblk, tmax), dim3(NT), kLds, s, a);
         return hipGetLastError();
     }
+    // the same kernels compiled with the friction cone (instances with mu > 0)
+    static hipError_t rollout_f(const KArgs& a, int nblk, hipStream_t s) {
+        hipLaunchKernelGGL((rollout_kernel<TOPO, NT, PPT, NOBS, true>), dim3(nblk), dim3(NT), kLds, s, a);
+        return hipGetLastError();
+    }
+    static hipError_t backward_f(const KArgs& a, int nblk, hipStream_t s) {
+        hipLaunchKernelGGL((backward_kernel<TOPO, NT, PPT, NOBS, true>), dim3(nblk), dim3(NT), kLds, s, a);
+        return hipGetLastError();
+    }
+    static hipError_t linearize_f(const KArgs& a, int nblk, int tmax, hipStream_t s) {
+        hipLaunchKernelGGL((linearize_kernel<TOPO, NT, PPT, NOBS, true>), dim3(nblk, tmax), dim3(NT), kLds, s, a);
+        return hipGetLastError();
+    }
     static int blocks_per_cu(int which) {
         int nb = 0;
         hipError_t e = which == 0
@@ -336,6 +349,7 @@ struct Launch {
 #define CORD_CFG(TOPO, NT, PPT, NOBS) \
     {TOPO, NT, PPT, NOBS, Launch<TOPO, NT, PPT, NOBS>::kLds, &Launch<TOPO, NT, PPT, NOBS>::rollout, \
      &Launch<TOPO, NT, PPT, NOBS>::backward, &Launch<TOPO, NT, PPT, NOBS>::linearize, \
-     &Launch<TOPO, NT, PPT, NOBS>::blocks_per_cu}
+     &Launch<TOPO, NT, PPT, NOBS>::blocks_per_cu, &Launch<TOPO, NT, PPT, NOBS>::rollout_f, \
+     &Launch<TOPO, NT, PPT, NOBS>::backward_f, &Launch<TOPO, NT, PPT, NOBS>::linearize_f}
 
 }  // namespace cord

@@ -344,25 +344,28 @@ bool enqueue(cord_server* s, Req* q) {
     a.ckpt_every = 1;
     a.status = q->d_status;
     const float reg = q->r.u_reg;
+    const bool fric = q->r.inst.params.mu > 0.f;
+    const auto roll = fric ? K.rollout_f : K.rollout;
+    const auto back = fric ? K.backward_f : K.backward;
     for (int it = 0; it < q->r.iters; ++it) {
         KArgs f = a;
         f.store = CORD_STORE_FULL;
         f.s0 = q->d_s0; f.u = q->d_u; f.traj = q->d_traj;
         f.aux = q->d_aux; f.aux_mode = 1;
-        SRV_HIP(K.rollout(f, C, st));
+        SRV_HIP(roll(f, C, st));
         SRV_HIP(plan_cost(q->d_inst, C, q->d_traj, q->d_u, q->r.goal_node, q->r.goal, reg, q->d_cost, q->d_sT, st));
         KArgs b = a;
         b.store = CORD_STORE_FULL;
         b.u = q->d_u; b.traj_in = q->d_traj; b.sT_bar = q->d_sT; b.s0_bar = q->d_s0b; b.u_bar = q->d_ub;
         b.aux = q->d_aux; b.aux_mode = 2;
-        SRV_HIP(K.backward(b, C, st));
+        SRV_HIP(back(b, C, st));
         SRV_HIP(plan_update(q->d_u, q->d_ub, (int64_t)C * T * nu, q->r.step, reg, q->r.u_max, st));
     }
     KArgs f = a;
     f.store = CORD_STORE_FULL;
     f.s0 = q->d_s0; f.u = q->d_u; f.traj = q->d_traj;
     f.aux = q->d_aux; f.aux_mode = 1;
-    SRV_HIP(K.rollout(f, C, st));
+    SRV_HIP(roll(f, C, st));
     SRV_HIP(plan_cost(q->d_inst, C, q->d_traj, q->d_u, q->r.goal_node, q->r.goal, reg, q->d_cost, nullptr, st));
     SRV_HIP(plan_argmin(q->d_cost, C, q->d_best, q->d_bcost, st));
     SRV_HIP(plan_status(q->d_status, C, q->d_simst, st));
@@ -380,8 +383,8 @@ bool enqueue(cord_server* s, Req* q) {
         SRV_HIP(launch_fill_i32(q->d_redo, T, 0, st));
         const int topo = q->r.inst.kind == CORD_ROPE ? kRope : kCloth;
         // one instance: the direct kernel keeps its vectors inside A (no scratch)
-        SRV_HIP(launch_linearize(q->cfg, topo, bucket_of(topo, q->n), q->r.inst.grip_mode == CORD_GRIP_PENALTY, l, 1,
-                                 T, st, KeptSource{&no_kept, nullptr}));
+        SRV_HIP(launch_linearize(q->cfg, topo, bucket_of(topo, q->n), q->r.inst.grip_mode == CORD_GRIP_PENALTY, fric,
+                                 l, 1, T, st, KeptSource{&no_kept, nullptr}));
     }
     // result download into the slot's staging
     char* h = sg.down;

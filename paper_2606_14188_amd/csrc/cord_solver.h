@@ -35,6 +35,7 @@ constexpr int kStNonFinite = 4;
 constexpr int kNewtonMax = 40;
 constexpr int kLineSearchMax = 30;
 constexpr int kIpmMax = 60;
+constexpr int kIpmFricMax = 150;        // friction cone: Newton steps over all relaxation levels
 constexpr int kPcgMax = 300;
 constexpr int kMinresMax = 600;
 constexpr float kMinresAccept = 1e-4f;  // true relative residual accepted after the last MINRES pass
@@ -221,7 +222,7 @@ constexpr int lds_floats() { return 12 * NT * PPT + 64 + 16 * kMaxGrip; }
 // polish (for the direct rope linearization, whose band factorizations
 // detect an indefinite dF/dq* themselves and hand such steps to the
 // iterative kernel, which has both).
-template <int TOPO, int NT, int PPT, int NOBS, bool FALLBACK = true>
+template <int TOPO, int NT, int PPT, int NOBS, bool FALLBACK = true, bool FRIC = false>
 struct Solver {
     static constexpr int NM = NT * PPT;
     static constexpr int NS = Topo<TOPO>::NS;
@@ -256,6 +257,14 @@ struct Solver {
     float Bd[PPT][6], Mi[PPT][6];
     float bw[PPT][3];       // rope: bending weights of the centres p-1, p, p+1 (zero if not a centre)
     float cn[PPT][NOBS][3], cphi[PPT][NOBS], clam[PPT][NOBS], cgap[PPT][NOBS];
+    // friction (mu > 0; compiled only into the FRIC instantiation): the tangential
+    // slack of each pair in its frame (n, t1, t2), and per particle the sum
+    // of its pairs' stiffness blocks (the contact part of the stage-2 matrix)
+    static constexpr int kFP = FRIC ? PPT : 1;
+    static constexpr int kFO = FRIC ? NOBS : 1;
+    float fmu;
+    float cy1[kFP][kFO], cy2[kFP][kFO];
+    float ck[kFP][6];
 
     int status;
     uint32_t cnt[4];   // Newton its, PCG its, interior-point its, steps
@@ -272,6 +281,7 @@ struct Solver {
     __device__ __forceinline__ void init(const InstDev& I, float* lds) {
         X = lds; D = X + 3 * NM; V = D + 3 * NM; DL = V + 3 * NM; rb = DL + 3 * NM; GR = rb + 64; rslot = 0;
         pmode = I.grip_mode; Dmax = I.D_max; khal = I.kappa_h; rgrip = I.r_g;
+        fmu = FRIC ? I.mu : 0.f;
         n = I.n; nx = I.nx; ny = I.ny; ngrip = I.n_grip; nobs = I.n_obs;
         h = I.h; mass = I.mass; dt = I.dt; gam = I.gamma; mdt2 = I.mass / (I.dt * I.dt);
         kb = (TOPO == kRope) ? I.k_bend : 0.f;
@@ -325,6 +335,137 @@ struct Solver {
             __builtin_amdgcn_wave_barrier();
         } else {
             __syncthreads();
+        }
+    }
+
+    // -------------------------------------------------- friction helpers
+    __device__ __forceinline__ bool friction() const {
+        if constexpr (FRIC) return fmu > 0.f;
+        else return false;
+    }
+    __device__ __forceinline__ static constexpr int fk(int k) { return FRIC ? k : 0; }
+    __device__ __forceinline__ static constexpr int fo(int o) { return FRIC ? o : 0; }
+    // unit tangents completing n to an orthonormal frame (any choice: the
+    // cone and its barrier are invariant under rotations about n)
+    __device__ __forceinline__ static void tframe(const float n[3], float t1[3], float t2[3]) {
+        const float a0 = fabsf(n[0]) < 0.9f ? 1.f : 0.f, a1 = 1.f - a0;   // a = e_x, or e_y
+        float c[3] = {-n[2] * a1, n[2] * a0, n[0] * a1 - n[1] * a0};       // n x a
+        const float il = 1.f / sqrtf(dot3(c, c));
+#pragma unroll
+        for (int i = 0; i < 3; ++i) t1[i] = c[i] * il;
+        t2[0] = n[1] * t1[2] - n[2] * t1[1];
+        t2[1] = n[2] * t1[0] - n[0] * t1[2];
+        t2[2] = n[0] * t1[1] - n[1] * t1[0];
+    }
+    // the largest a > 0 with y + a dy inside the cone {y0 > mu |(y1, y2)|}
+    // (y inside): the smallest positive root of Q(a) = y0(a)^2 - mu^2 |y_t(a)|^2
+    // or of y0(a), whichever comes first
+    __device__ __forceinline__ static float cone_step(float y0, float y1, float y2, float d0, float d1, float d2,
+                                                      float m2) {
+        float am = 1e30f;
+        if (d0 < 0.f) am = -y0 / d0;
+        const float A = d0 * d0 - m2 * (d1 * d1 + d2 * d2);
+        const float B = 2.f * (y0 * d0 - m2 * (y1 * d1 + y2 * d2));
+        const float C = y0 * y0 - m2 * (y1 * y1 + y2 * y2);
+        const float disc = B * B - 4.f * A * C;
+        if (disc >= 0.f) {
+            const float q = -0.5f * (B + copysignf(sqrtf(disc), B));
+            if (q != 0.f) {
+                const float r1 = C / q;
+                if (r1 > 0.f) am = fminf(am, r1);
+            }
+            if (A != 0.f) {
+                const float r2 = q / A;
+                if (r2 > 0.f) am = fminf(am, r2);
+            }
+        }
+        return am;
+    }
+    // One pair with friction at the stage-2 correction D = dl[k]: u = d + D
+    // (the node's displacement over the step), y_n = phi + n.D, tau = T u,
+    // Q = y_n^2 - mu^2 |tau|^2, a = y_n n - mu^2 tau, w = kappa / Q; the
+    // force is w a.  Returns false for an invalid pair.
+    struct Pair {
+        float n[3], H[6], u[3], tau[3], a[3], Hu[3], HD[3];
+        float yn, nu, Q, w;
+    };
+    __device__ __forceinline__ void fric_pair(int k, int o, float kappa, const float yst[3], Pair& P) const {
+        const float m2 = fmu * fmu;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { P.n[c] = cn[k][o][c]; P.u[c] = d[k][c] + dl[k][c]; }
+        sdf_hess(otype[o], ob[o], yst, P.H);
+        P.yn = cphi[k][o] + dot3(P.n, dl[k]);
+        P.nu = dot3(P.n, P.u);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) P.tau[c] = P.u[c] - P.nu * P.n[c];
+        P.Q = P.yn * P.yn - m2 * dot3(P.tau, P.tau);
+        P.w = kappa / P.Q;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) P.a[c] = P.yn * P.n[c] - m2 * P.tau[c];
+        sym_mul(P.H, P.u, P.Hu);
+        sym_mul(P.H, dl[k], P.HD);
+    }
+    // ck[k] = sum of the pairs' blocks K_c = w (2 a a^T / Q - (1 + mu^2) n n^T + mu^2 I)
+    // (minus the derivative of the force in D) at relaxation kappa
+    __device__ __forceinline__ void fric_blocks(float kappa) {
+        const float m2 = fmu * fmu;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) ck[fk(k)][i] = 0.f;
+            if (!isfree(k)) continue;
+            float yst[3] = {x[k][0] + d[k][0], x[k][1] + d[k][1], x[k][2] + d[k][2]};
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) {
+                if (o >= nobs) continue;
+                Pair P;
+                fric_pair(k, o, kappa, yst, P);
+                sym_add_outer(ck[fk(k)], 2.f * P.w / P.Q, P.a);
+                sym_add_outer(ck[fk(k)], -P.w * (1.f + m2), P.n);
+                ck[fk(k)][0] += P.w * m2;
+                ck[fk(k)][3] += P.w * m2;
+                ck[fk(k)][5] += P.w * m2;
+            }
+        }
+    }
+    // dlam/dq* of a pair applied to r (forward) or transposed (adjoint):
+    //   Ly = w (A_y - a q_y^T / Q),
+    //   A_y = n (n + H D)^T + y_n H + mu^2 ((n.u) H + n (H u)^T - T),
+    //   q_y = 2 y_n (n + H D) + 2 mu^2 (n.u) H tau - 2 mu^2 tau;
+    // dlam/dx of the pair's node: Lx = w (mu^2 T - 2 mu^2 a tau^T / Q).
+    __device__ __forceinline__ void fric_ly(const Pair& P, const float r[3], bool transpose, float out[3]) const {
+        const float m2 = fmu * fmu;
+        float nH[3], Hr[3], Htau[3], qy[3], Tr[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nH[c] = P.n[c] + P.HD[c];
+        sym_mul(P.H, r, Hr);
+        sym_mul(P.H, P.tau, Htau);
+        const float nr = dot3(P.n, r);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            qy[c] = 2.f * P.yn * nH[c] + 2.f * m2 * P.nu * Htau[c] - 2.f * m2 * P.tau[c];
+            Tr[c] = r[c] - nr * P.n[c];
+        }
+        if (!transpose) {
+            const float s1 = dot3(nH, r), s2 = dot3(P.Hu, r), s3 = dot3(qy, r) / P.Q;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                out[c] = P.w * (P.n[c] * s1 + P.yn * Hr[c] + m2 * (P.nu * Hr[c] + P.n[c] * s2 - Tr[c]) - P.a[c] * s3);
+        } else {
+            const float s3 = dot3(P.a, r) / P.Q;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                out[c] = P.w * (nH[c] * nr + P.yn * Hr[c] + m2 * (P.nu * Hr[c] + P.Hu[c] * nr - Tr[c]) - qy[c] * s3);
+        }
+    }
+    __device__ __forceinline__ void fric_lx(const Pair& P, const float r[3], bool transpose, float out[3]) const {
+        const float m2 = fmu * fmu;
+        const float nr = dot3(P.n, r);
+        const float s = transpose ? dot3(P.a, r) / P.Q : dot3(P.tau, r) / P.Q;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float Tr = r[c] - nr * P.n[c];
+            out[c] = P.w * m2 * (Tr - 2.f * (transpose ? P.tau[c] : P.a[c]) * s);
         }
     }
 
@@ -594,12 +735,24 @@ struct Solver {
             }
             if constexpr (CONTACT) {
                 if (isfree(k)) {
+                    bool fr = false;
+                    if constexpr (FRIC) {
+                        if (friction()) {
+                            float t[3];
+                            sym_mul(ck[fk(k)], wp, t);
 #pragma unroll
-                    for (int o = 0; o < NOBS; ++o) {
-                        if (o >= nobs) continue;
-                        const float w = clam[k][o] / cgap[k][o] * dot3(cn[k][o], wp);
+                            for (int c = 0; c < 3; ++c) q[k][c] += t[c];
+                            fr = true;
+                        }
+                    }
+                    if (!fr) {
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) q[k][c] += w * cn[k][o][c];
+                        for (int o = 0; o < NOBS; ++o) {
+                            if (o >= nobs) continue;
+                            const float w = clam[k][o] / cgap[k][o] * dot3(cn[k][o], wp);
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) q[k][c] += w * cn[k][o][c];
+                        }
                     }
                 }
             }
@@ -628,9 +781,19 @@ struct Solver {
                 if (!(m[0] > 0.f && m2 > 0.f && m3 > 0.f)) pcpd = 0.f;
             }
             if constexpr (CONTACT) {
+                bool fr = false;
+                if constexpr (FRIC) {
+                    if (friction()) {
 #pragma unroll
-                for (int o = 0; o < NOBS; ++o)
-                    if (o < nobs) sym_add_outer(m, clam[k][o] / cgap[k][o], cn[k][o]);
+                        for (int i = 0; i < 6; ++i) m[i] += ck[fk(k)][i];
+                        fr = true;
+                    }
+                }
+                if (!fr) {
+#pragma unroll
+                    for (int o = 0; o < NOBS; ++o)
+                        if (o < nobs) sym_add_outer(m, clam[k][o] / cgap[k][o], cn[k][o]);
+                }
             }
             if (isfree(k)) sym_inv(m, Mi[k]);
             else {
@@ -1011,6 +1174,12 @@ struct Solver {
     // solved by a primal-dual interior point from an infeasible start.
     // kappa > 0: mu = kappa.  kappa = 0: mu is driven towards 0 (hard contact).
     __device__ __forceinline__ void stage2(float kappa) {
+        if constexpr (FRIC) {
+            if (friction()) {
+                stage2_friction(kappa);
+                return;
+            }
+        }
         float F[PPT][3];
         grad_cache(false, F);      // exact Hessian data at y*
         eval_contacts();
@@ -1141,6 +1310,194 @@ struct Solver {
         else if constexpr (FALLBACK) {
             if (hard) hard_polish();
         }
+    }
+
+    // Stage 2 with the friction cone (eq. contact-constraint, Anitescu's
+    // relaxation).  Per pair the constraint value y = [phi + n.D ; t1.(d + D) ;
+    // t2.(d + D)] (normal row at y*, tangential rows the node's displacement
+    // over the step) must lie in the dual cone {y0 >= mu |(y1, y2)|}.
+    // Smoothed: the central-path point of min 1/2 D^T P D - kappa sum psi(y),
+    // psi = 1/2 log(y0^2 - mu^2 (y1^2 + y2^2)), so lam = kappa grad psi lies in
+    // the cone and y . lam = kappa.  Newton from an infeasible start on D and
+    // the slack y (cgap, cy1, cy2) with lam = kappa grad psi(y): residuals
+    // r_D = P D - sum J^T lam, r_p = y - J D - b; the step solves
+    // (P + sum J^T Hb J) dD = -r_D + sum J^T Hb r_p (Hb = -kappa Hess psi, per
+    // particle summed into ck), dy = J dD - r_p, and stays inside the cone.
+    // Hard (kappa = 0): the relaxation is lowered tenfold after each
+    // converged level down to 1e-7 fscale h.
+    __device__ __forceinline__ void stage2_friction(float kappa) {
+        float F[PPT][3];
+        grad_cache(false, F);      // exact Hessian data at y*
+        eval_contacts();
+        const bool hard = !(kappa > 0.f);
+        const float m2 = fmu * fmu;
+        const float kmin = 1e-7f * fscale * h;
+        float kk = kappa;
+        if (hard) {
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                for (int o = 0; o < NOBS; ++o)
+                    if (o < nobs && isfree(k)) {
+                        float t[3];
+                        sym_mul(Bd[k], cn[k][o], t);
+                        acc += dot3(cn[k][o], t) * cphi[k][o] * cphi[k][o];
+                    }
+            acc = bsum(acc);
+            kk = fmaxf(1e-2f * acc / fmaxf((float)((n - ngrip) * nobs), 1.f), kmin);
+        }
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dl[k][c] = 0.f;
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) {
+                clam[k][o] = 0.f;
+                cgap[k][o] = 1.f;
+                cy1[fk(k)][fo(o)] = 0.f;
+                cy2[fk(k)][fo(o)] = 0.f;
+                if (o < nobs && isfree(k)) {
+                    float t1[3], t2[3], t[3];
+                    tframe(cn[k][o], t1, t2);
+                    sym_mul(Bd[k], cn[k][o], t);
+                    const float pi = fmaxf(dot3(cn[k][o], t), mdt2);
+                    const float s1 = dot3(t1, d[k]), s2 = dot3(t2, d[k]);
+                    cy1[fk(k)][fo(o)] = s1;
+                    cy2[fk(k)][fo(o)] = s2;
+                    cgap[k][o] = fmaxf(cphi[k][o], 0.f) + fmu * sqrtf(s1 * s1 + s2 * s2) + sqrtf(kk / pi);
+                }
+            }
+        }
+        if (nobs == 0) return;
+        bool conv = false;
+        for (int it = 0; it < kIpmFricMax; ++it) {
+            float rd[PPT][3], rhs[PPT][3];
+            float rp[PPT][NOBS][3];
+            publish(V, dl);
+            apply<false>(rd);
+            float err = 0.f;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                float fm = fmaxf(fabsf(rd[k][0]), fmaxf(fabsf(rd[k][1]), fabsf(rd[k][2])));
+#pragma unroll
+                for (int i = 0; i < 6; ++i) ck[fk(k)][i] = 0.f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rhs[k][c] = 0.f;
+#pragma unroll
+                for (int o = 0; o < NOBS; ++o) {
+                    rp[k][o][0] = rp[k][o][1] = rp[k][o][2] = 0.f;
+                    if (!(o < nobs && isfree(k))) continue;
+                    float t1[3], t2[3], u[3];
+                    tframe(cn[k][o], t1, t2);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) u[c] = d[k][c] + dl[k][c];
+                    const float y0 = cgap[k][o], y1 = cy1[fk(k)][fo(o)], y2 = cy2[fk(k)][fo(o)];
+                    rp[k][o][0] = y0 - cphi[k][o] - dot3(cn[k][o], dl[k]);
+                    rp[k][o][1] = y1 - dot3(t1, u);
+                    rp[k][o][2] = y2 - dot3(t2, u);
+                    const float iq = 1.f / (y0 * y0 - m2 * (y1 * y1 + y2 * y2));
+                    const float g[3] = {y0 * iq, -m2 * y1 * iq, -m2 * y2 * iq};
+                    // Hb = kappa (2 g g^T - diag(1, -mu^2, -mu^2) / Q), in the pair's frame
+                    const float Hb[6] = {kk * (2.f * g[0] * g[0] - iq), kk * 2.f * g[0] * g[1], kk * 2.f * g[0] * g[2],
+                                         kk * (2.f * g[1] * g[1] + m2 * iq), kk * 2.f * g[1] * g[2],
+                                         kk * (2.f * g[2] * g[2] + m2 * iq)};
+                    float hr[3];
+                    sym_mul(Hb, rp[k][o], hr);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        rd[k][c] -= kk * (g[0] * cn[k][o][c] + g[1] * t1[c] + g[2] * t2[c]);
+                        rhs[k][c] += hr[0] * cn[k][o][c] + hr[1] * t1[c] + hr[2] * t2[c];
+                    }
+                    // ck += R^T Hb R, R = rows (n, t1, t2)
+                    const float* e[3] = {cn[k][o], t1, t2};
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const float hii = Hb[i == 0 ? 0 : (i == 1 ? 3 : 5)];
+                        sym_add_outer(ck[fk(k)], hii, e[i]);
+                    }
+                    // off-diagonal frame terms Hb_ij (e_i e_j^T + e_j e_i^T)
+                    const int oi[3] = {0, 0, 1}, oj[3] = {1, 2, 2}, oh[3] = {1, 2, 4};
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        const float hv = Hb[oh[q]];
+                        const float* a = e[oi[q]];
+                        const float* b = e[oj[q]];
+                        ck[fk(k)][0] += 2.f * hv * a[0] * b[0];
+                        ck[fk(k)][1] += hv * (a[0] * b[1] + a[1] * b[0]);
+                        ck[fk(k)][2] += hv * (a[0] * b[2] + a[2] * b[0]);
+                        ck[fk(k)][3] += 2.f * hv * a[1] * b[1];
+                        ck[fk(k)][4] += hv * (a[1] * b[2] + a[2] * b[1]);
+                        ck[fk(k)][5] += 2.f * hv * a[2] * b[2];
+                    }
+                    fm += kk * fabsf(g[0]);
+                    const float gt = kTolGap * (h + fabsf(cphi[k][o]));
+                    err = nmax(err, fmaxf(fabsf(rp[k][o][0]), fmaxf(fabsf(rp[k][o][1]), fabsf(rp[k][o][2]))) / gt);
+                }
+                const float tolD = tolF + 5e-7f * fm;
+                if (isfree(k))
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) err = nmax(err, fabsf(rd[k][c]) / tolD);
+            }
+            err = bmax(finite_key(err));
+            if (err >= kBad) { status = max(status, kStNonFinite); return; }
+            if (err <= 1.f) {
+                if (hard && kk > kmin) {
+                    kk = fmaxf(0.1f * kk, kmin);
+                    continue;
+                }
+                conv = true;
+                break;
+            }
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rhs[k][c] = isfree(k) ? rhs[k][c] - rd[k][c] : 0.f;
+            float dD[PPT][3];
+            build_precond<true>();
+            solve<true>(rhs, dD, kPcgTolInner);
+            ++cnt[2];
+            float amax = 1.f / 0.995f;
+            float dy[PPT][NOBS][3];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+#pragma unroll
+                for (int o = 0; o < NOBS; ++o) {
+                    dy[k][o][0] = dy[k][o][1] = dy[k][o][2] = 0.f;
+                    if (!(o < nobs && isfree(k))) continue;
+                    float t1[3], t2[3];
+                    tframe(cn[k][o], t1, t2);
+                    dy[k][o][0] = dot3(cn[k][o], dD[k]) - rp[k][o][0];
+                    dy[k][o][1] = dot3(t1, dD[k]) - rp[k][o][1];
+                    dy[k][o][2] = dot3(t2, dD[k]) - rp[k][o][2];
+                    amax = fminf(amax, cone_step(cgap[k][o], cy1[fk(k)][fo(o)], cy2[fk(k)][fo(o)], dy[k][o][0],
+                                                 dy[k][o][1], dy[k][o][2], m2));
+                }
+            amax = bmin(amax);
+            const float alpha = fminf(1.f, 0.995f * amax);
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) dl[k][c] += alpha * dD[k][c];
+#pragma unroll
+                for (int o = 0; o < NOBS; ++o)
+                    if (o < nobs && isfree(k)) {
+                        cgap[k][o] += alpha * dy[k][o][0];
+                        cy1[fk(k)][fo(o)] += alpha * dy[k][o][1];
+                        cy2[fk(k)][fo(o)] += alpha * dy[k][o][2];
+                    }
+            }
+        }
+        if (!conv) status = max(status, kStQP);
+        // normal force of each pair (kept with the step internals)
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o)
+                if (o < nobs && isfree(k)) {
+                    const float y0 = cgap[k][o], y1 = cy1[fk(k)][fo(o)], y2 = cy2[fk(k)][fo(o)];
+                    clam[k][o] = kk * y0 / (y0 * y0 - m2 * (y1 * y1 + y2 * y2));
+                }
     }
 
     // Hard contact: the interior point ends with a small positive lam * gap
@@ -1454,9 +1811,19 @@ struct Solver {
                 qb[k][c] = isfree(k) ? xb[k][c] + vb[k][c] * idt : 0.f;
                 bb[k][c] = (active(k) && !isfree(k)) ? xb[k][c] : 0.f;
             }
-        // stage 2: z = K^{-1} qb, K = P + N^T Lam N
+        // stage 2: z = K^{-1} qb, K = P + N^T Lam N (with friction P + sum K_c)
+        if constexpr (FRIC) {
+            if (friction()) fric_blocks(kappa);
+        }
         build_precond<true>();
         solve<true>(qb, z, kPcgTolAdj);
+        // friction: the step depends on x directly through the tangential
+        // displacement; its cotangent Lx^T z joins xb below
+        float xadd[PPT][3];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) xadd[k][c] = 0.f;
         // e1 = (C - W - R^T - N^T Lam N) z ; gripped rows: bb -= (W z)_g
         publish(V, z);
         apply_third(t2, true);
@@ -1473,6 +1840,25 @@ struct Solver {
 #pragma unroll
             for (int c = 0; c < 3; ++c) e1[k][c] = -t2[k][c];
             float yst[3] = {x[k][0] + d[k][0], x[k][1] + d[k][1], x[k][2] + d[k][2]};
+            if constexpr (FRIC) {
+                if (friction()) {
+                    // e1 gains sum_c Ly_c^T z, xb gains sum_c Lx_c^T z
+#pragma unroll
+                    for (int o = 0; o < NOBS; ++o) {
+                        if (o >= nobs) continue;
+                        Pair P;
+                        fric_pair(k, o, kappa, yst, P);
+                        float t[3];
+                        fric_ly(P, z[k], true, t);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) e1[k][c] += t[c];
+                        fric_lx(P, z[k], true, t);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) xadd[k][c] += t[c];
+                    }
+                    continue;
+                }
+            }
 #pragma unroll
             for (int o = 0; o < NOBS; ++o) {
                 if (o >= nobs) continue;
@@ -1513,9 +1899,9 @@ struct Solver {
             if (isfree(k)) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    dxb[k][c] = del[k][c];
+                    dxb[k][c] = del[k][c] + xadd[k][c];
                     vb[k][c] = dt * (1.f - gam) * (qb[k][c] + del[k][c]);
-                    xb[k][c] += del[k][c];
+                    xb[k][c] += del[k][c] + xadd[k][c];
                     ubk[k][c] = 0.f;
                 }
                 if (pen[k] >= 0) {
@@ -1612,6 +1998,25 @@ struct Solver {
             for (int c = 0; c < 3; ++c) r2[k][c] = isfree(k) ? -t2[k][c] : 0.f;
             if (!isfree(k)) continue;
             float yst[3] = {x[k][0] + d[k][0], x[k][1] + d[k][1], x[k][2] + d[k][2]};
+            if constexpr (FRIC) {
+                if (friction()) {
+                    // r2 gains sum_c (Ly_c dy + Lx_c dx)
+#pragma unroll
+                    for (int o = 0; o < NOBS; ++o) {
+                        if (o >= nobs) continue;
+                        Pair P;
+                        fric_pair(k, o, kappa, yst, P);
+                        float t[3], dxk[3] = {dx[k][0], dx[k][1], dx[k][2]};
+                        fric_ly(P, dy[k], false, t);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) r2[k][c] += t[c];
+                        fric_lx(P, dxk, false, t);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) r2[k][c] += t[c];
+                    }
+                    continue;
+                }
+            }
 #pragma unroll
             for (int o = 0; o < NOBS; ++o) {
                 if (o >= nobs) continue;
@@ -1632,6 +2037,9 @@ struct Solver {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) r2[k][c] -= pdk[k] * dl[k][c];
         float eta[PPT][3];
+        if constexpr (FRIC) {
+            if (friction()) fric_blocks(kappa);
+        }
         build_precond<true>();
         solve<true>(r2, eta, kPcgTolAdj);
 #pragma unroll

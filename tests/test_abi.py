@@ -50,7 +50,7 @@ def _create(descs):
 
 @pytest.mark.parametrize("field,value,code", [
     ("dt", 0.0, 1), ("gamma", 1.5, 1), ("kappa_bwd", 0.0, 1), ("kappa_fwd", -1.0, 1),
-    ("mu", 0.3, 4), ("T", 0, 1), ("mass", 0.0, 1), ("ny", 2, 1), ("grip", 99, 1),
+    ("mu", -0.3, 1), ("mu", float("nan"), 1), ("T", 0, 1), ("mass", 0.0, 1), ("ny", 2, 1), ("grip", 99, 1),
     ("nspheres", 5, 1), ("n_inst0", 0, 1), ("nx", 0, 1), ("nx", 257, 4),
 ])
 def test_validation_errors(field, value, code):

@@ -1,0 +1,143 @@
+"""Friction cone (eq. contact-constraint, mu > 0) on the GPU against the
+oracle: a particle under gravity tilted below and above the friction angle,
+ropes dragged over the ground and over half-sunk spheres with
+smoothed contact (states, rollout gradient, dense A_t/B_t and JVP tangents
+per step, by the row-by-row kernel), a batch that mixes friction with
+frictionless instances of the same size class, and the refusal of hard
+contact with friction at the boundary."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.derivatives import StepDerivative, rollout_backward
+from oracle.step import rollout as orollout
+from tests.parity import (GRAD_TOL, JAC_TOL, STATE_TOL, check, gradient_block_errors, jacobian_block_errors,
+                          state_errors, tangent_block_errors)
+
+pytestmark = pytest.mark.gpu
+
+
+def _particle(mu, theta, kappa):
+    g = 9.81 * np.array([np.sin(theta), 0.0, -np.cos(theta)])
+    inst = W.rope(1, grip_nodes=(), gravity=tuple(g), gamma=1.0, z0=0.0, T=3, u=np.zeros((3, 0)), h=0.01)
+    return inst.replace(mu=mu, kappa_fwd=kappa, kappa_bwd=kappa)
+
+
+def test_tilted_plane_particle_smoothed():
+    """A particle on the ground under gravity tilted below and above the
+    friction angle, with a small relaxation: the GPU step follows the
+    oracle's, and the particle slides far more above tan(theta) = mu."""
+    import torch
+    from paper_2606_14188_amd import Sim
+    mu, kappa = 0.3, 1e-7
+    thetas = (0.15, 0.25, 0.35, 0.6, 1.0)
+    insts = [_particle(mu, th, kappa) for th in thetas]
+    sim = Sim(insts)
+    st = torch.full((len(insts),), -1, dtype=torch.int32, device=sim.device)
+    traj = sim.rollout(sim.pack_states([i.s0 for i in insts]), sim.pack_controls([i.u for i in insts]), status=st)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all(), st
+    parts = sim.split(traj, "traj")
+    a = insts[0].dt ** 2 * 9.81
+    for inst, tr, th in zip(insts, parts, thetas):
+        ref, rst = orollout(inst)
+        assert rst.max() == 0
+        ex, ev = state_errors(tr, ref, 1)
+        x1 = tr.reshape(inst.T + 1, -1)[1]
+        print(f"theta {th}: x after one step {x1[:3]}, oracle {ref[1][:3]}; err x {ex:.2e} v {ev:.2e}", flush=True)
+        assert ex <= STATE_TOL and ev <= STATE_TOL
+        if np.tan(th) > mu + 0.05:
+            assert x1[0] > 0.5 * a * (np.sin(th) - mu * np.cos(th)) / (1 + mu * mu)
+        if np.tan(th) < mu - 0.05:
+            assert abs(x1[0]) < 0.1 * a
+
+
+def test_hard_contact_with_friction_is_refused():
+    """Friction needs a smoothed forward step on the GPU (the oracle has the
+    hard limit): the boundary refuses kappa_fwd = 0 with mu > 0."""
+    from paper_2606_14188_amd import CordError, Sim
+    from paper_2606_14188_amd import _lib as L
+    with pytest.raises(CordError) as e:
+        Sim(W.friction_ropes(1, n=12, T=3, seed=1025, hard=True))
+    assert e.value.code == L.CORD_EUNSUPPORTED
+
+
+def _states_and_gradient(insts, label):
+    import torch
+    from paper_2606_14188_amd import Sim
+    sim = Sim(insts)
+    s0 = sim.pack_states([i.s0 for i in insts])
+    u = sim.pack_controls([i.u for i in insts])
+    st = torch.full((len(insts),), -1, dtype=torch.int32, device=sim.device)
+    traj = sim.rollout(s0, u, status=st)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all(), st
+    parts = sim.split(traj, "traj")
+    for j, inst in enumerate(insts):
+        ref, rst = orollout(inst)
+        assert rst.max() == 0
+        ex, ev = state_errors(parts[j], ref, inst.n)
+        print(f"{label} {j} mu={inst.mu:.2f}: state err x {ex:.2e} v {ev:.2e}", flush=True)
+        assert ex <= STATE_TOL and ev <= STATE_TOL
+    rng = np.random.default_rng(1022)
+    cot = [rng.normal(size=i.n_s) for i in insts]
+    st.fill_(-1)
+    s0b, ub = sim.backward(u, traj, sT_bar=sim.pack_states(cot), status=st)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all(), st
+    sp, up = sim.split(s0b, "s"), sim.split(ub, "u")
+    for j, inst in enumerate(insts):
+        tr = parts[j].reshape(inst.T + 1, inst.n_s).astype(np.float64)
+        s0r, ur = rollout_backward(inst, tr, sT_bar=cot[j])
+        check(gradient_block_errors(sp[j], up[j], s0r, ur, inst.n), GRAD_TOL, f"{label} {j} gradient")
+    return sim, traj, u, parts
+
+
+def test_dragged_ropes_smoothed_states_gradient_jacobians():
+    import torch
+    insts = W.friction_ropes(4, n=12, T=8, seed=1023)
+    sim, traj, u, parts = _states_and_gradient(insts, "rope")
+    k = 2
+    rng = np.random.default_rng(1024)
+    ds = [rng.normal(size=(i.T, k, i.n_s)) for i in insts]
+    du = [rng.normal(size=(i.T, k, i.n_u)) for i in insts]
+    status = torch.full((len(insts),), -1, dtype=torch.int32, device=sim.device)
+    A, Bm, jv = sim.linearize(traj, u, jvp_k=k, jvp_ds=sim.pack_states([d.ravel() for d in ds]),
+                              jvp_du=sim.pack_states([d.ravel() for d in du]), status=status)
+    torch.cuda.synchronize()
+    assert (status.cpu().numpy() == 0).all(), status
+    Ap, Bp = sim.split(A, "A"), sim.split(Bm, "B")
+    h = jv.cpu().numpy()
+    off = 0
+    for j, inst in enumerate(insts):
+        ns, nu = inst.n_s, inst.n_u
+        tr = parts[j].reshape(inst.T + 1, ns).astype(np.float64)
+        blk = h[off:off + inst.T * k * ns].reshape(inst.T, k, ns)
+        off += inst.T * k * ns
+        for t in range(inst.T):
+            d = StepDerivative(inst, tr[t], inst.u[t], inst.kappa_bwd)
+            Ar, Br = d.dense()
+            errs = jacobian_block_errors(Ap[j].reshape(inst.T, ns, ns)[t], Ar, Bp[j].reshape(inst.T, ns, nu)[t],
+                                         Br, inst.n)
+            errs.update(tangent_block_errors(blk[t], d.jvp_s(ds[j][t].T, du[j][t].T).T, inst.n))
+            check(errs, JAC_TOL, f"rope {j} t={t}")
+
+
+def test_friction_and_frictionless_in_one_class():
+    """Instances with and without friction share a size class: the class
+    runs the friction kernels, and the frictionless instances keep their
+    own result (checked against the oracle and against a frictionless-only
+    launch)."""
+    import torch
+    from paper_2606_14188_amd import Sim
+    fr = W.friction_ropes(2, n=12, T=6, seed=1026)
+    plain = [i.replace(mu=0.0) for i in W.friction_ropes(2, n=12, T=6, seed=1027)]
+    mixed = [fr[0], plain[0], fr[1], plain[1]]
+    _states_and_gradient(mixed, "mixed")
+    sa, sb = Sim(mixed), Sim(plain)
+    ta = sa.rollout(sa.pack_states([i.s0 for i in mixed]), sa.pack_controls([i.u for i in mixed]))
+    tb = sb.rollout(sb.pack_states([i.s0 for i in plain]), sb.pack_controls([i.u for i in plain]))
+    torch.cuda.synchronize()
+    pa, pb = sa.split(ta, "traj"), sb.split(tb, "traj")
+    for a, b in ((pa[1], pb[0]), (pa[3], pb[1])):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-6 * np.max(np.abs(b)))

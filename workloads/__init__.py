@@ -23,4 +23,5 @@ from .gen import (  # noqa: F401
     calibration_set,
     lift_rope_envs,
     sls_system,
+    friction_ropes,
 )

@@ -417,3 +417,24 @@ def sls_system(B: int, N: int, n: int, m: int, seed: int = 1016, r: float = 0.05
     K = -0.2 * s * rng.normal(size=(B, N + 1, m, n))
     f32 = lambda x: np.ascontiguousarray(x, dtype=np.float32)  # noqa: E731
     return dict(A=f32(A), E=f32(E), F=f32(F), Xi=f32(Xi), Bm=f32(Bm), K=f32(K))
+
+
+def friction_ropes(B: int, n: int = 12, T: int = 10, seed: int = 1021, hard: bool = False):
+    """Ropes dragged over the ground with friction: n nodes, 0.4 m, lying at
+    z = 1 mm (inside the smoothing width of the ground), some with a sphere
+    half sunk in the ground on their path; node 0 held by the gripper, whose
+    velocity is mostly along the rope (N(0.15, 0.05^2), N(0, 0.05^2), 0) so
+    that the rope slides; mu ~ U[0.2, 0.8].  hard: kappa_fwd = 0 (the
+    paper's forward mode), gradients smoothed."""
+    out = []
+    for rng in _streams(seed, B):
+        mu = float(rng.uniform(0.2, 0.8))
+        spheres = [[float(rng.uniform(0.15, 0.3)), float(rng.uniform(-0.05, 0.05)), -0.02, 0.03]] \
+            if rng.uniform() < 0.5 else []
+        u = np.stack([rng.normal(0.15, 0.05, T), rng.normal(0.0, 0.05, T), np.zeros(T)], axis=1)
+        inst = rope(n, length=0.4, z0=0.001, T=T, grip_nodes=(0,), spheres=spheres, u=u)
+        inst = inst.replace(mu=mu)
+        if hard:
+            inst = inst.replace(kappa_fwd=0.0)
+        out.append(inst)
+    return out
