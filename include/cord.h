@@ -584,7 +584,11 @@ int cord_server_stats(cord_server* srv, int64_t* out8);
  * cord_sls_kalman: the Kalman recursion (eq. kalman_recursions),
  * Pi_0 = Xi Xi^T, L_{j+1} = -(F_j F_j^T + Pi_j)^{-1} Pi_j A_j^T,
  * Pi_{j+1} = E_j E_j^T + A_j Pi_j A_j^T + A_j Pi_j L_{j+1}, either
- * CORD_SLS_SERIAL (one workgroup per instance steps through the horizon) or
+ * CORD_SLS_SERIAL (one workgroup per instance steps through the horizon,
+ * each step in the scan elements' form Pi' = E E^T + W^T Pi A^T with
+ * W = (I + (F F^T)^{-1} Pi)^{-1} A^T, L = W - A^T, which is the same
+ * recursion without the subtraction that FP32 cannot resolve when the
+ * measurements are accurate) or
  * CORD_SLS_SCAN (the associative scan of eqs. combination_rules and
  * initialization, ceil(log2(N+1)) rounds, then all gains at once).
  * status: device int32[B], CORD_ST_NOT_PD where a solve met a zero or

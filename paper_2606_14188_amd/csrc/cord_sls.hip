@@ -292,18 +292,51 @@ __device__ bool kalman_step(const Args& a, const float* A, const float* Qw, cons
     return ok;
 }
 
-// grid (B): the recursion run serially over the horizon, one workgroup per instance.
+// One Kalman step in the form of the scan's elements, free of cancellation:
+// with Dinv = (F F^T)^{-1}, W = (I + Dinv Pi)^{-1} A^T,
+//   Pi' = E E^T + W^T (Pi A^T),   L = W - A^T.
+// (Pi' = E E^T + A (Pi^{-1} + Dinv)^{-1} A^T adds a positive semidefinite
+// term; the printed form A Pi A^T + A Pi L subtracts two nearly equal
+// matrices when the measurements are accurate (F F^T << Pi), which FP32
+// cannot resolve.  L = -(F F^T + Pi)^{-1} Pi A^T = W - A^T since
+// (I + Dinv Pi)^{-1} = (F F^T + Pi)^{-1} F F^T.)
+__device__ bool kalman_step_stable(const Args& a, const float* A, const float* Qw, const float* Dinv, const float* Pi,
+                                   float* L, float* Pn, float* slot, float* lds) {
+    const int n = a.n;
+    float* X = slot;
+    float* G = gbuf(a, lds, slot + nn(a));
+    wg_gemm(G, 2 * n, Dinv, n, false, Pi, n, false, n, n, n, 1.f, nullptr, 0, nullptr, 0, 1.f, lds);
+    for (int x = threadIdx.x; x < n * n; x += kThreads) {
+        const int r = x / n, c = x - r * n;
+        G[(size_t)r * 2 * n + n + c] = A[(size_t)c * n + r];
+    }
+    __syncthreads();
+    const bool ok = wg_solve(G, 2 * n, n, n, lds + kGemmLds - 2 * kThreads);
+    for (int x = threadIdx.x; x < n * n; x += kThreads) {
+        const int r = x / n, c = x - r * n;
+        L[x] = G[(size_t)r * 2 * n + n + c] - A[(size_t)c * n + r];
+    }
+    wg_gemm(X, n, Pi, n, false, A, n, true, n, n, n, 1.f, nullptr, 0, nullptr, 0, 0.f, lds);
+    wg_gemm(Pn, n, G + n, 2 * n, true, X, n, false, n, n, n, 1.f, Qw, n, nullptr, 0, 0.f, lds);
+    return ok;
+}
+
+// grid (B): the recursion run serially over the horizon, one workgroup per
+// instance (the scan's step elements give Dinv).
 __global__ __launch_bounds__(kThreads) void kalman_serial_kernel(Args a) {
     extern __shared__ float lds[];
     const int b = blockIdx.x, n = a.n;
     float* slot = a.ws + (size_t)b * a.ws_stride;
     float* Pi = a.Pi + (size_t)b * (a.N + 1) * nn(a);
+    const float* el = a.el[0] + (size_t)b * (a.N + 1) * 3 * nn(a);
     wg_gemm(Pi, n, a.Xi + (size_t)b * nn(a), n, false, a.Xi + (size_t)b * nn(a), n, true, n, n, n, 1.f, nullptr, 0,
             nullptr, 0, 0.f, lds);
     bool ok = true;
     for (int j = 0; j < a.N; ++j) {
         const size_t o = ((size_t)b * a.N + j) * nn(a);
-        ok &= kalman_step(a, a.A + o, a.Qw + o, a.Rv + o, Pi + j * nn(a), a.L + o, Pi + (j + 1) * nn(a), slot, lds);
+        const float* Dinv = el + (size_t)(j + 1) * 3 * nn(a) + nn(a);
+        ok &= kalman_step_stable(a, a.A + o, a.Qw + o, Dinv, Pi + j * nn(a), a.L + o, Pi + (j + 1) * nn(a), slot,
+                                 lds);
     }
     flag(a, b, ok);
 }
@@ -506,6 +539,120 @@ __global__ __launch_bounds__(kThreads) void tri_gemm_kernel(int rows, int cols, 
             N, k1 - k0, alpha, a1, cols, a2, cols, 0.f, lds);
 }
 
+// The same product with 128 x 128 output tiles for the large assembly
+// operators: each wavefront a 64 x 64 quarter (4 x 4 blocks of
+// v_mfma_f32_16x16x4f32, 64 accumulators), K in chunks of 16 staged through
+// two LDS buffers (the next chunk is loaded into registers while the
+// current one is multiplied), rows read as float2 (every row and tile
+// offset is even).  grid (tiles_c, tiles_r, batch).
+constexpr int kBT = 128, kBK = 16;
+constexpr int kBPadA = kBK + 1, kBPadB = kBT + 1;
+constexpr int kBBuf = kBT * kBPadA + kBK * kBPadB;
+constexpr int kBigLds = 2 * kBBuf;
+
+__global__ __launch_bounds__(kThreads) void tri_gemm128_kernel(int rows, int cols, int K, int ra, int n, float alpha,
+                                                               const float* A, const float* Bm, const float* add1,
+                                                               const float* add2, float* C) {
+    extern __shared__ float lds[];
+    const int tn = blockIdx.x * kBT, tm = blockIdx.y * kBT, b = blockIdx.z;
+    const size_t sa = (size_t)rows * K, sb = (size_t)K * cols, sc = (size_t)rows * cols;
+    const int r1 = min(rows, tm + kBT);
+    const int c1 = min(cols, tn + kBT);
+    const int k0 = (tn / n) * n;
+    const int k1 = min(K, ((r1 - 1) / ra + 1) * n);
+    const float* Ab = A + b * sa;
+    const float* Bb = Bm + b * sb;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
+    const int l16 = lane & 15, lk = lane >> 4;
+    f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    // per thread: A rows ar, k columns ac..ac+7; B row br, columns bc..bc+7
+    const int ar = tid >> 1, ac = (tid & 1) * 8;
+    const int br = tid >> 4, bc = (tid & 15) * 8;
+    float ra_[8], rb_[8];
+    auto load = [&](int kc) {
+        const int gr = tm + ar;
+#pragma unroll
+        for (int q = 0; q < 8; q += 2) {
+            const int gk = kc + ac + q;
+            float2 v = make_float2(0.f, 0.f);
+            if (gr < r1 && gk + 1 < k1) v = *reinterpret_cast<const float2*>(Ab + (size_t)gr * K + gk);
+            else if (gr < r1 && gk < k1) v.x = Ab[(size_t)gr * K + gk];
+            ra_[q] = v.x;
+            ra_[q + 1] = v.y;
+        }
+        const int gk = kc + br;
+#pragma unroll
+        for (int q = 0; q < 8; q += 2) {
+            const int gc = tn + bc + q;
+            float2 v = make_float2(0.f, 0.f);
+            if (gk < k1 && gc + 1 < c1) v = *reinterpret_cast<const float2*>(Bb + (size_t)gk * cols + gc);
+            else if (gk < k1 && gc < c1) v.x = Bb[(size_t)gk * cols + gc];
+            rb_[q] = v.x;
+            rb_[q + 1] = v.y;
+        }
+    };
+    auto store = [&](int buf) {
+        float* As = lds + buf * kBBuf;
+        float* Bs = As + kBT * kBPadA;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) As[ar * kBPadA + ac + q] = ra_[q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Bs[br * kBPadB + bc + q] = rb_[q];
+    };
+    if (k1 > k0) {
+        load(k0);
+        store(0);
+        __syncthreads();
+        int buf = 0;
+        for (int kc = k0; kc < k1; kc += kBK) {
+            const bool more = kc + kBK < k1;
+            if (more) load(kc + kBK);
+            const float* As = lds + buf * kBBuf;
+            const float* Bs = As + kBT * kBPadA;
+#pragma unroll
+            for (int kk = 0; kk < kBK; kk += 4) {
+                const int kr = kk + lk;
+                float a[4], bv[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = As[(wm + 16 * i + l16) * kBPadA + kr];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bv[j] = Bs[kr * kBPadB + wn + 16 * j + l16];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bv[j], acc[i][j], 0, 0, 0);
+            }
+            if (more) store(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+    float* Cb = C + b * sc;
+    const float* a1 = add1 ? add1 + b * sc : nullptr;
+    const float* a2 = add2 ? add2 + b * sc : nullptr;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = tm + wm + 16 * i + 4 * lk + v;
+                const int c = tn + wn + 16 * j + l16;
+                if (r < r1 && c < c1) {
+                    float x = alpha * acc[i][j][v];
+                    if (a1) x += a1[(size_t)r * cols + c];
+                    if (a2) x += a2[(size_t)r * cols + c];
+                    Cb[(size_t)r * cols + c] = x;
+                }
+            }
+}
+
 // ---------------------------------------------------------------- tubes
 // grid (N, N+1, B), workgroup (j, k) with j < k: the row norms of
 // Pw_{k,j+1} E_j and of Pe_{k,j+1} F_j for the dense Pw, Pe ((N+1) rr x D),
@@ -678,7 +825,8 @@ int cord_sls_kalman(cord_sls* s, const float* A, const float* E, const float* F,
     a.L = L;
     a.status = status;
     SLS_HIP(cord::launch_fill_i32(status, s->B, CORD_ST_OK, st));
-    hipLaunchKernelGGL(prep_kernel, dim3(s->N, s->B), dim3(kThreads), lb, st, a, scan ? 1 : 0);
+    // both modes use the step elements (the serial step takes Dinv from them)
+    hipLaunchKernelGGL(prep_kernel, dim3(s->N, s->B), dim3(kThreads), lb, st, a, 1);
     SLS_HIP(hipGetLastError());
     if (!scan) {
         hipLaunchKernelGGL(kalman_serial_kernel, dim3(s->B), dim3(kThreads), lb, st, a);
@@ -766,21 +914,27 @@ int cord_sls_assemble(cord_sls* s, const float* A, const float* Pbx, const float
     SLS_HIP(hipGetLastError());
     hipLaunchKernelGGL(shift_kernel, gs, dim3(kThreads), lb, st, s->N, n, D, A, Phy, s->MY);
     SLS_HIP(hipGetLastError());
-    const dim3 gx((D + kTile - 1) / kTile, (D + kTile - 1) / kTile, s->B);
-    const dim3 gu((D + kTile - 1) / kTile, (Du + kTile - 1) / kTile, s->B);
+    // even row lengths and block offsets let the big-tile kernel read float2;
+    // otherwise the 64 x 64 kernel
+    const bool big = (D % 2 == 0) && (n % 2 == 0);
+    const int T = big ? kBT : kTile;
+    const size_t lbig = big ? sizeof(float) * kBigLds : lb;
+    auto tri = big ? tri_gemm128_kernel : tri_gemm_kernel;
+    const dim3 gx((D + T - 1) / T, (D + T - 1) / T, s->B);
+    const dim3 gu((D + T - 1) / T, (Du + T - 1) / T, s->B);
     // Phi^xw = Phibar^x + Phihat^x - Phibar^x M Phihat^x
-    hipLaunchKernelGGL(tri_gemm_kernel, gx, dim3(kThreads), lb, st, D, D, D, n, n, -1.f, Pbx, s->MX, Pbx, Phx, Pxw);
+    hipLaunchKernelGGL(tri, gx, dim3(kThreads), lbig, st, D, D, D, n, n, -1.f, Pbx, s->MX, Pbx, Phx, Pxw);
     SLS_HIP(hipGetLastError());
     // Phi^uw = Phibar^u - Phibar^u M Phihat^x
-    hipLaunchKernelGGL(tri_gemm_kernel, gu, dim3(kThreads), lb, st, Du, D, D, m, n, -1.f, Pbu, s->MX, Pbu,
+    hipLaunchKernelGGL(tri, gu, dim3(kThreads), lbig, st, Du, D, D, m, n, -1.f, Pbu, s->MX, Pbu,
                        (const float*)nullptr, Puw);
     SLS_HIP(hipGetLastError());
     // Phi^xe = Phihat^y - Phibar^x M Phihat^y
-    hipLaunchKernelGGL(tri_gemm_kernel, gx, dim3(kThreads), lb, st, D, D, D, n, n, -1.f, Pbx, s->MY, Phy,
+    hipLaunchKernelGGL(tri, gx, dim3(kThreads), lbig, st, D, D, D, n, n, -1.f, Pbx, s->MY, Phy,
                        (const float*)nullptr, Pxe);
     SLS_HIP(hipGetLastError());
     // Phi^ue = -Phibar^u M Phihat^y
-    hipLaunchKernelGGL(tri_gemm_kernel, gu, dim3(kThreads), lb, st, Du, D, D, m, n, -1.f, Pbu, s->MY,
+    hipLaunchKernelGGL(tri, gu, dim3(kThreads), lbig, st, Du, D, D, m, n, -1.f, Pbu, s->MY,
                        (const float*)nullptr, (const float*)nullptr, Pue);
     SLS_HIP(hipGetLastError());
     return CORD_OK;
