@@ -141,3 +141,26 @@ def test_friction_and_frictionless_in_one_class():
     pa, pb = sa.split(ta, "traj"), sb.split(tb, "traj")
     for a, b in ((pa[1], pb[0]), (pa[3], pb[1])):
         np.testing.assert_allclose(a, b, rtol=0, atol=1e-6 * np.max(np.abs(b)))
+
+
+def test_dragged_cloths_smoothed():
+    """Cloths dragged over the ground by two corners (the cloth size
+    classes' friction kernels, several particles per thread): states and
+    rollout gradient against the oracle, and dense A_t/B_t blocks at the
+    first and last step."""
+    import torch
+    insts = W.friction_cloths(2, side=8, T=5, seed=1028)
+    sim, traj, u, parts = _states_and_gradient(insts, "cloth")
+    status = torch.full((len(insts),), -1, dtype=torch.int32, device=sim.device)
+    A, Bm, _ = sim.linearize(traj, u, status=status)
+    torch.cuda.synchronize()
+    assert (status.cpu().numpy() == 0).all(), status
+    Ap, Bp = sim.split(A, "A"), sim.split(Bm, "B")
+    for j, inst in enumerate(insts):
+        ns, nu = inst.n_s, inst.n_u
+        tr = parts[j].reshape(inst.T + 1, ns).astype(np.float64)
+        for t in (0, inst.T - 1):
+            Ar, Br = StepDerivative(inst, tr[t], inst.u[t], inst.kappa_bwd).dense()
+            errs = jacobian_block_errors(Ap[j].reshape(inst.T, ns, ns)[t], Ar, Bp[j].reshape(inst.T, ns, nu)[t],
+                                         Br, inst.n)
+            check(errs, JAC_TOL, f"cloth {j} t={t}")

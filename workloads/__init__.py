@@ -24,4 +24,5 @@ from .gen import (  # noqa: F401
     lift_rope_envs,
     sls_system,
     friction_ropes,
+    friction_cloths,
 )

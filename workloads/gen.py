@@ -438,3 +438,20 @@ def friction_ropes(B: int, n: int = 12, T: int = 10, seed: int = 1021, hard: boo
             inst = inst.replace(kappa_fwd=0.0)
         out.append(inst)
     return out
+
+
+def friction_cloths(B: int, side: int = 8, T: int = 6, seed: int = 1028):
+    """Square cloths (side x side nodes, 0.2 m) lying at z = 1 mm on the
+    ground with friction mu ~ U[0.3, 0.7], the two corners of one edge
+    gripped and dragged along the ground (u ~ N(0.1, 0.03^2) along x and
+    N(0, 0.03^2) along y for both grippers, 0 vertically)."""
+    out = []
+    for rng in _streams(seed, B):
+        mu = float(rng.uniform(0.3, 0.7))
+        u = np.zeros((T, 6))
+        for g in range(2):
+            u[:, 3 * g] = rng.normal(0.1, 0.03, T)
+            u[:, 3 * g + 1] = rng.normal(0.0, 0.03, T)
+        inst = cloth(side, side, size=0.2, z0=0.001, T=T, u=u)
+        out.append(inst.replace(mu=mu))
+    return out
