@@ -320,6 +320,98 @@ def bench_sls(args):
     return out
 
 
+def bench_next(args):
+    """The widened rows: friction (the C2 batch of 1024 ropes x 64 nodes x
+    100 steps, forward + adjoint, frictionless and with mu = 0.5 on every
+    contact; dense A_t/B_t of 64 of them with friction, by the row-by-row
+    kernel), analytical policy gradients (one training iteration of the
+    lift task: 64 environments x 20 steps, forward and backward through
+    the simulator and the policy), and the conformal radius (scores of
+    10 000 calibration transitions and the order statistic)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2606_14188_amd import Sim, cp_radius
+    from paper_2606_14188_amd.apg import MLPPolicy, lift_loss, policy_rollout, sim_step
+    out = {}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    reps = max(3, args.steps)
+    # friction at the C2 size
+    base = workload()
+    B, n, T = len(base), base[0].n, base[0].T
+    fr = {}
+    for label, insts in (("frictionless", base), ("mu_0.5", [i.replace(mu=0.5) for i in base])):
+        sim = Sim(insts)
+        s0 = sim.pack_states([i.s0 for i in insts])
+        u = sim.pack_controls([i.u for i in insts])
+        traj = torch.empty(sim.info.traj_floats, dtype=torch.float32, device=sim.device)
+        sT = sim.pack_states([W.random_cotangent(i.n_s, 7000 + j) for j, i in enumerate(insts)])
+        st = torch.zeros(B, dtype=torch.int32, device=sim.device)
+        ms_f = timed(lambda: sim.rollout(s0, u, out=traj, status=st), reps)
+        ms_b = timed(lambda: sim.backward(u, traj, sT_bar=sT), reps)
+        fr[label] = {"rollout_ms": ms_f, "backward_ms": ms_b,
+                     "particle_steps_per_s": B * n * T / ((ms_f + ms_b) / 1e3),
+                     "status_nonzero": int((st.cpu().numpy() != 0).sum())}
+        del sim, traj
+        torch.cuda.empty_cache()
+    sub = [i.replace(mu=0.5) for i in base[:64]]
+    sim = Sim(sub)
+    s0 = sim.pack_states([i.s0 for i in sub])
+    u = sim.pack_controls([i.u for i in sub])
+    traj = sim.rollout(s0, u)
+    A = torch.empty(sim.info.A_floats, dtype=torch.float32, device=sim.device)
+    Bm = torch.empty(sim.info.B_floats, dtype=torch.float32, device=sim.device)
+    fr["mu_0.5_linearize_64_ms"] = timed(lambda: sim.linearize(traj, u, A=A, Bm=Bm), reps)
+    del sim, traj, A, Bm
+    torch.cuda.empty_cache()
+    out["friction"] = {"workload": f"rope-{n} x {B}, T={T}: forward + adjoint; A_t/B_t of 64 with friction", **fr}
+    # analytical policy gradients
+    torch.manual_seed(5)
+    envs = W.lift_rope_envs(64, n=12, seed=1011)
+    sim = Sim(envs)
+    policy = MLPPolicy(u_max=0.5).to(sim.device)
+    s0 = sim.pack_states([i.s0 for i in envs]).reshape(len(envs), -1)
+    step = sim_step(sim)
+    Tl = 20
+
+    def it():
+        policy.zero_grad()
+        sT, us = policy_rollout(step, policy, s0, 12, Tl)
+        lift_loss(sT, us, 12, 0.02).backward()
+
+    ms_it = timed(it, reps)
+    out["apg"] = {"workload": "lift task: 64 environments x 20 steps, rope-12 with penalty grippers, "
+                              "hard forward / smoothed gradient", "ms_per_iteration": ms_it,
+                  "env_steps_per_s": 64 * Tl / (ms_it / 1e3)}
+    del sim
+    # conformal radius
+    cal = W.calibration_set(10000, seed=1030)
+    insts = [c[0] for c in cal]
+    sim = Sim(insts)
+    s0 = sim.pack_states([i.s0 for i in insts])
+    u = sim.pack_controls([i.u for i in insts])
+    s_next = sim.pack_states([np.concatenate([c[1].ravel(), np.zeros(3 * c[0].n)]) for c in cal])
+    ms_s = timed(lambda: sim.cp_scores(s0, u, s_next), reps)
+    sc = sim.cp_scores(s0, u, s_next)
+    ms_r = timed(lambda: cp_radius(sc, 0.05, 40), reps)
+    out["conformal"] = {"workload": "10000 calibration transitions of an 11-node rope", "scores_ms": ms_s,
+                        "radius_ms": ms_r, "radius_m": float(cp_radius(sc, 0.05, 40)[0])}
+    return out
+
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 PROFILE = os.path.join(HERE, "profiles", "rollout_backward_linearize__rope64x1024_T100.md")
 LIN_SOURCES = ["cord_lin_direct.h", "cord_solver.h", "cord_lin_rope.hip"]
@@ -486,7 +578,7 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes (default: host cores, at most 16)")
     ap.add_argument("--cpu-sample", type=int, default=32, help="oracle instances of the rope batch")
     ap.add_argument("--cpu-T", type=int, default=100)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "probe", "copy", "sls"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "probe", "copy", "sls", "next"])
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=22.0,
                     help="length of the Poisson trace of the serving leg (the first 2 s are discarded)")
@@ -496,7 +588,7 @@ def main():
     ap.add_argument("--grasp", default="dirichlet", choices=["dirichlet", "penalty"],
                     help="grasp of the rope batch (penalty: holonomic penalty with smoothed activation)")
     ap.add_argument("--no-serve", action="store_true", help="skip the planning-stream leg")
-    ap.add_argument("--no-extras", action="store_true", help="skip the cloth (C3), mixed-batch (C4) and SLS legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the cloth (C3), mixed-batch (C4), SLS and widened-row legs")
     ap.add_argument("--overlap", action="store_true",
                     help="run the adjoint and the linearization concurrently on two streams, both after "
                          "the rollout (default: one after the other on one stream, so that each kernel's "
@@ -522,6 +614,9 @@ def main():
         return
     if args.workload == "sls":
         print(json.dumps(bench_sls(args)), flush=True)
+        return
+    if args.workload == "next":
+        print(json.dumps(bench_next(args)), flush=True)
         return
 
     with_lin = not args.no_linearize
@@ -655,7 +750,7 @@ def main():
     # there is recorded instead of losing the line)
     if not args.no_extras:
         extras = {}
-        for name, fn in (("c3", bench_c3), ("c4", bench_c4), ("sls", bench_sls)):
+        for name, fn in (("c3", bench_c3), ("c4", bench_c4), ("sls", bench_sls), ("next", bench_next)):
             try:
                 extras[name] = fn(args)
             except Exception as e:      # noqa: BLE001
