@@ -49,30 +49,38 @@ __global__ void cp_init_kernel(float* radius, int32_t* rank, float value) {
 __device__ __forceinline__ float cp_key(float s) { return s == s ? s : INFINITY; }
 
 // The score at 0-based position k0 of the ascending order, ties broken by
-// index: thread i counts the scores below s_i, and the equal ones of lower
-// index, over tiles of 256 scores staged in LDS; (score, index) is a total
-// order, so exactly one thread finds the count k0 and writes its score and
-// index.
-__global__ __launch_bounds__(256) void cp_rank_kernel(const float* scores, int n, int k0, float* radius,
-                                                      int32_t* rank) {
-    __shared__ float tile[256];
-    const int i = blockIdx.x * 256 + threadIdx.x;
+// index.  (score, index) is a total order, so the position of score i is
+// the number of scores below it plus the equal ones of lower index, and
+// exactly one i has position k0.  A workgroup takes 16 candidates i and
+// splits the n scores into 16 ranges: thread (r, c) counts candidate c
+// against range r, the 16 partial counts of a candidate are summed in LDS,
+// and the candidate whose count is k0 writes its score and index.  The
+// counts are exact integers, so the split does not change the selection.
+constexpr int kCpCand = 16;    // candidates per workgroup
+constexpr int kCpRanges = 16;  // ranges of the scores per candidate
+__global__ __launch_bounds__(kCpCand * kCpRanges) void cp_rank_kernel(const float* scores, int n, int k0,
+                                                                      float* radius, int32_t* rank) {
+    __shared__ int part[kCpRanges][kCpCand];
+    const int c = threadIdx.x % kCpCand, r = threadIdx.x / kCpCand;
+    const int i = blockIdx.x * kCpCand + c;
     const float si = i < n ? cp_key(scores[i]) : 0.f;
+    const int len = (n + kCpRanges - 1) / kCpRanges;
+    const int j0 = r * len, j1 = min(n, j0 + len);
     int below = 0;
-    for (int t0 = 0; t0 < n; t0 += 256) {
-        __syncthreads();
-        const int j = t0 + threadIdx.x;
-        tile[threadIdx.x] = j < n ? cp_key(scores[j]) : 0.f;
-        __syncthreads();
-        const int cnt = min(256, n - t0);
-        for (int jj = 0; jj < cnt; ++jj) {
-            const float sj = tile[jj];
-            below += (sj < si || (sj == si && t0 + jj < i)) ? 1 : 0;
-        }
+    for (int j = j0; j < j1; ++j) {
+        const float sj = cp_key(scores[j]);
+        below += (sj < si || (sj == si && j < i)) ? 1 : 0;
     }
-    if (i < n && below == k0) {
-        *radius = scores[i];
-        if (rank) *rank = i;
+    part[r][c] = below;
+    __syncthreads();
+    if (r == 0 && i < n) {
+        int tot = 0;
+#pragma unroll
+        for (int q = 0; q < kCpRanges; ++q) tot += part[q][c];
+        if (tot == k0) {
+            *radius = scores[i];
+            if (rank) *rank = i;
+        }
     }
 }
 
@@ -81,7 +89,8 @@ hipError_t launch_cp_radius(const float* scores, int n, int k, float* radius, in
     hipLaunchKernelGGL(cp_init_kernel, dim3(1), dim3(64), 0, s, radius, rank, k > n ? INFINITY : NAN);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || k > n) return e;
-    hipLaunchKernelGGL(cp_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, s, scores, n, k - 1, radius, rank);
+    hipLaunchKernelGGL(cp_rank_kernel, dim3((n + kCpCand - 1) / kCpCand), dim3(kCpCand * kCpRanges), 0, s, scores,
+                       n, k - 1, radius, rank);
     return hipGetLastError();
 }
 

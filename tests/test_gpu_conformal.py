@@ -48,3 +48,31 @@ def test_cp_scores_and_radius_match_oracle():
     r, idx = cp_radius(sc[:9], 0.05, 1)           # k = ceil(10 * 0.95) = 10 > 9
     torch.cuda.synchronize()
     assert math.isinf(r.item()) and int(idx.item()) == -1
+
+
+@pytest.mark.parametrize("n", [1, 17, 10000, 65536])
+def test_cp_radius_order_statistic_with_ties_and_nan(n):
+    """The radius kernel on FP32 scores with many exact ties and 2 % NaN
+    (a failed rollout's score orders last), up to the largest accepted n:
+    the value the oracle's rule selects, and the index of that position in
+    the order (score, index), NaN as +inf."""
+    import torch
+    from paper_2606_14188_amd import cp_radius
+    rng = np.random.default_rng(1030 + n)
+    s = np.round(rng.gamma(2.0, 1e-3, size=n), 5).astype(np.float32)
+    if n > 1:
+        s[rng.choice(n, size=max(1, n // 50), replace=False)] = np.nan
+    dev = torch.from_numpy(s).cuda()
+    key = np.where(np.isnan(s), np.inf, s.astype(np.float64))
+    order = np.argsort(key, kind="stable")
+    for delta, T in ((0.1, 1), (0.02, 1), (0.5, 2), (0.9, 1), (0.3, 30)):
+        r, idx = cp_radius(dev, delta, T)
+        torch.cuda.synchronize()
+        r, idx = float(r.item()), int(idx.item())
+        r_or, k = conformal.radius(s, delta, T)
+        print(f"n {n} delta {delta} T {T}: k {k} radius gpu {r} oracle {r_or} index {idx}", flush=True)
+        if k > n:
+            assert math.isinf(r) and idx == -1
+            continue
+        assert idx == order[k - 1]
+        assert (math.isnan(r) and math.isnan(r_or)) or r == np.float32(r_or)
