@@ -48,7 +48,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // for r < M, c < N.  op(X)[r][c] = tX ? X[c ldx + r] : X[r ldx + c].  Pointers
 // may point to global memory or LDS; C must not overlap A or B (add1/add2 may
 // be C itself).  Ends with a barrier: C is visible to the whole workgroup.
-__device__ void wg_gemm(float* C, int ldc, const float* A, int lda, bool tA, const float* B, int ldb, bool tB,
+__device__ __forceinline__ void wg_gemm(float* C, int ldc, const float* A, int lda, bool tA, const float* B, int ldb, bool tB,
                         int M, int N, int K, float alpha, const float* add1, int ld1, const float* add2, int ld2,
                         float diag, float* lds) {
     float* As = lds;
@@ -56,29 +56,55 @@ __device__ void wg_gemm(float* C, int ldc, const float* A, int lda, bool tA, con
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
     const int l16 = lane & 15, lk = lane >> 4;
+    // operand elements per thread and chunk: loaded into registers one
+    // chunk ahead, so the loads of chunk k+1 are in flight during the
+    // products of chunk k
+    constexpr int kPer = kTile * kChunk / kThreads;
+    float va[kPer], vb[kPer];
+    // element q of this thread: op(A) row ra0 + q dra, column ca0 + q dca
+    // (inside the chunk), and likewise for op(B)
+    const int ra0 = tA ? (tid & 63) : (tid >> 5), ca0 = tA ? (tid >> 6) : (tid & 31);
+    const int dra = tA ? 0 : kThreads / kChunk, dca = tA ? kThreads / kTile : 0;
+    const int rb0 = tB ? (tid & 31) : (tid >> 6), cb0 = tB ? (tid >> 5) : (tid & 63);
+    const int drb = tB ? 0 : kThreads / kTile, dcb = tB ? kThreads / kChunk : 0;
+    auto load = [&](int tm, int tn, int k0) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int gr = tm + ra0 + q * dra, gc = k0 + ca0 + q * dca;
+            const size_t off = tA ? (size_t)gc * lda + gr : (size_t)gr * lda + gc;
+            va[q] = (gr < M && gc < K) ? A[off] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int gr = k0 + rb0 + q * drb, gc = tn + cb0 + q * dcb;
+            const size_t off = tB ? (size_t)gc * ldb + gr : (size_t)gr * ldb + gc;
+            vb[q] = (gr < K && gc < N) ? B[off] : 0.f;
+        }
+    };
+    load(0, 0, 0);
     for (int tm = 0; tm < M; tm += kTile)
         for (int tn = 0; tn < N; tn += kTile) {
             f4 acc[2][2];
             for (int i = 0; i < 2; ++i)
                 for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
             for (int k0 = 0; k0 < K; k0 += kChunk) {
-                for (int e = tid; e < kTile * kChunk; e += kThreads) {
-                    const int r = tA ? (e & 63) : (e >> 5);
-                    const int c = tA ? (e >> 6) : (e & 31);
-                    const int gr = tm + r, gc = k0 + c;
-                    float v = 0.f;
-                    if (gr < M && gc < K) v = tA ? A[(size_t)gc * lda + gr] : A[(size_t)gr * lda + gc];
-                    As[r * kPadA + c] = v;
-                }
-                for (int e = tid; e < kChunk * kTile; e += kThreads) {
-                    const int r = tB ? (e & 31) : (e >> 6);
-                    const int c = tB ? (e >> 5) : (e & 63);
-                    const int gr = k0 + r, gc = tn + c;
-                    float v = 0.f;
-                    if (gr < K && gc < N) v = tB ? B[(size_t)gc * ldb + gr] : B[(size_t)gr * ldb + gc];
-                    Bs[r * kPadB + c] = v;
+#pragma unroll
+                for (int q = 0; q < kPer; ++q) {
+                    As[(ra0 + q * dra) * kPadA + ca0 + q * dca] = va[q];
+                    Bs[(rb0 + q * drb) * kPadB + cb0 + q * dcb] = vb[q];
                 }
                 __syncthreads();
+                // the next chunk of this tile, else the first chunk of the next
+                // tile (past the last tile every element is out of range)
+                {
+                    int nm = tm, nn_ = tn, nk = k0 + kChunk;
+                    if (nk >= K) {
+                        nk = 0;
+                        nn_ = tn + kTile;
+                        if (nn_ >= N) { nn_ = 0; nm = tm + kTile; }
+                    }
+                    load(nm, nn_, nk);
+                }
 #pragma unroll
                 for (int kk = 0; kk < kChunk; kk += 4) {
                     const int kr = kk + lk;
@@ -93,43 +119,89 @@ __device__ void wg_gemm(float* C, int ldc, const float* A, int lda, bool tA, con
                 }
                 __syncthreads();
             }
-            // accumulator v of lane l: row 4 (l / 16) + v, column l % 16 of its 16 x 16 block
+            // accumulator v of lane l: row 4 (l / 16) + v, column l % 16 of its
+            // 16 x 16 block.  The addends of a block are read before any of
+            // its elements of C is written (each element is read and written
+            // by its own thread, so C may be add1 or add2).
+#pragma unroll
             for (int i = 0; i < 2; ++i)
-                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int r0 = tm + wm + 16 * i + 4 * lk, c = tn + wn + 16 * j + l16;
+                    float ad1[4], ad2[4];
+#pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int r = tm + wm + 16 * i + 4 * lk + v;
-                        const int c = tn + wn + 16 * j + l16;
+                        const bool in = r0 + v < M && c < N;
+                        ad1[v] = (add1 && in) ? add1[(size_t)(r0 + v) * ld1 + c] : 0.f;
+                        ad2[v] = (add2 && in) ? add2[(size_t)(r0 + v) * ld2 + c] : 0.f;
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = r0 + v;
                         if (r < M && c < N) {
                             float x = alpha * acc[i][j][v];
-                            if (add1) x += add1[(size_t)r * ld1 + c];
-                            if (add2) x += add2[(size_t)r * ld2 + c];
+                            if (add1) x += ad1[v];
+                            if (add2) x += ad2[v];
                             if (r == c) x += diag;
                             C[(size_t)r * ldc + c] = x;
                         }
                     }
+                }
         }
     __syncthreads();
 }
 
-// dst[r][c] = alpha src[r][c] (+ beta I), workgroup-wide, ends with a barrier.
-__device__ void wg_copy(float* dst, int ldd, const float* src, int lds_, int M, int N, float alpha, float diag) {
-    for (int e = threadIdx.x; e < M * N; e += kThreads) {
-        const int r = e / N, c = e - r * N;
-        dst[(size_t)r * ldd + c] = alpha * src[(size_t)r * lds_ + c] + (r == c ? diag : 0.f);
+// Element-wise pass over `total` elements by the workgroup: st(e, ld(e)).
+// Four elements per thread are loaded before any is stored, so the loads
+// are in flight together (stores through a pointer that may alias the
+// sources would otherwise order each load after the previous store).  An
+// element is loaded and stored by the same thread, so dst may alias src
+// element for element.  No barrier.
+template <class Ld, class St>
+__device__ __forceinline__ void wg_map(int total, Ld ld, St st) {
+    for (int e0 = threadIdx.x; e0 < total; e0 += 4 * kThreads) {
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = e0 + q * kThreads;
+            v[q] = e < total ? ld(e) : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = e0 + q * kThreads;
+            if (e < total) st(e, v[q]);
+        }
     }
+}
+
+// dst[r][c] = alpha src[r][c] (+ beta I), workgroup-wide, ends with a barrier.
+__device__ __forceinline__ void wg_copy(float* dst, int ldd, const float* src, int lds_, int M, int N, float alpha, float diag) {
+    wg_map(
+        M * N,
+        [&](int e) {
+            const int r = e / N, c = e - r * N;
+            return src[(size_t)r * lds_ + c];
+        },
+        [&](int e, float v) {
+            const int r = e / N, c = e - r * N;
+            dst[(size_t)r * ldd + c] = alpha * v + (r == c ? diag : 0.f);
+        });
     __syncthreads();
 }
 
 // dst = src^T (n x n), workgroup-wide, ends with a barrier.
-__device__ void wg_transpose(float* dst, const float* src, int n) {
-    for (int e = threadIdx.x; e < n * n; e += kThreads) {
-        const int r = e / n, c = e - r * n;
-        dst[(size_t)r * n + c] = src[(size_t)c * n + r];
-    }
+__device__ __forceinline__ void wg_transpose(float* dst, const float* src, int n) {
+    wg_map(
+        n * n,
+        [&](int e) {
+            const int r = e / n, c = e - r * n;
+            return src[(size_t)c * n + r];
+        },
+        [&](int e, float v) { dst[e] = v; });
     __syncthreads();
 }
 
-__device__ void wg_zero(float* dst, int ldd, int M, int N) {
+__device__ __forceinline__ void wg_zero(float* dst, int ldd, int M, int N) {
     for (int e = threadIdx.x; e < M * N; e += kThreads) {
         const int r = e / N, c = e - r * N;
         dst[(size_t)r * ldd + c] = 0.f;
@@ -137,7 +209,7 @@ __device__ void wg_zero(float* dst, int ldd, int M, int N) {
     __syncthreads();
 }
 
-__device__ void wg_ident(float* dst, int ldd, int n) {
+__device__ __forceinline__ void wg_ident(float* dst, int ldd, int n) {
     for (int e = threadIdx.x; e < n * n; e += kThreads) {
         const int r = e / n, c = e - r * n;
         dst[(size_t)r * ldd + c] = r == c ? 1.f : 0.f;
@@ -146,34 +218,52 @@ __device__ void wg_ident(float* dst, int ldd, int n) {
 }
 
 // ---------------------------------------------------------------- workgroup solve
+// A lane's value from the lane that the DPP control CTRL names (all rows and
+// banks enabled).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
 // Gauss-Jordan with partial pivoting on G = [M | R] (n rows, ld = n + m):
 // on return G[:, n : n + m] = M^{-1} R.  Returns false if a pivot is zero or
 // not finite.  `red` is 2 * kThreads floats of LDS.  Per column: the first
-// wavefront finds the pivot with shuffles (no barrier inside), then one
-// barrier each after the search, the row swap and the elimination.
-__device__ bool wg_solve(float* G, int ld, int n, int m, float* red) {
+// wavefront finds the pivot with DPP and lane reads (no barrier inside),
+// then one barrier each after the search, the row swap and the
+// elimination.
+__device__ __forceinline__ bool wg_solve(float* G, int ld, int n, int m, float* red) {
     const int tid = threadIdx.x;
     const int W = n + m;
     int* pidx = reinterpret_cast<int*>(red);
     bool ok = true;
     for (int k = 0; k < n; ++k) {
         if (tid < 64) {
-            // the largest |G[i][k]| for i >= k, lowest row on ties
-            float best = -1.f, bv = 0.f;
-            int bi = n;
+            // the largest |G[i][k]| for i >= k, lowest row on ties, as the
+            // largest key (bits of |v|, ~i) (the bits of a non-negative
+            // float order like its value; a NaN counts as 0).  Maximum
+            // inside rows of 16 lanes by DPP, then across the four rows.
+            uint32_t hi = 0u, lo = 0u;
             for (int i = k + tid; i < n; i += 64) {
-                const float v = G[(size_t)i * ld + k];
-                if (fabsf(v) > best) { best = fabsf(v); bv = v; bi = i; }
+                const float a = fabsf(G[i * ld + k]);
+                const uint32_t h = a == a ? __float_as_uint(a) : 0u, l = ~(uint32_t)i;
+                if (h > hi || (h == hi && l > lo)) { hi = h; lo = l; }
             }
-            for (int o = 32; o >= 1; o >>= 1) {
-                const float ob = __shfl_xor(best, o, 64);
-                const float ov = __shfl_xor(bv, o, 64);
-                const int oi = __shfl_xor(bi, o, 64);
-                if (ob > best || (ob == best && oi < bi)) { best = ob; bv = ov; bi = oi; }
-            }
+            auto take = [&](uint32_t oh, uint32_t ol) {
+                if (oh > hi || (oh == hi && ol > lo)) { hi = oh; lo = ol; }
+            };
+            take(dpp_u32<0xB1>(hi), dpp_u32<0xB1>(lo));     // quad_perm [1,0,3,2]
+            take(dpp_u32<0x4E>(hi), dpp_u32<0x4E>(lo));     // quad_perm [2,3,0,1]
+            take(dpp_u32<0x141>(hi), dpp_u32<0x141>(lo));   // row_half_mirror
+            take(dpp_u32<0x140>(hi), dpp_u32<0x140>(lo));   // row_mirror
+#pragma unroll
+            for (int r = 16; r < 64; r += 16)
+                take((uint32_t)__builtin_amdgcn_readlane((int)hi, r), (uint32_t)__builtin_amdgcn_readlane((int)lo, r));
+            hi = (uint32_t)__builtin_amdgcn_readlane((int)hi, 0);
+            lo = (uint32_t)__builtin_amdgcn_readlane((int)lo, 0);
             if (tid == 0) {
-                pidx[0] = bi < n ? bi : k;
-                red[1] = bi < n ? bv : G[(size_t)k * ld + k];
+                const int bi = (int)~lo;
+                pidx[0] = bi;
+                red[1] = G[bi * ld + k];
             }
         }
         __syncthreads();
@@ -183,23 +273,43 @@ __device__ bool wg_solve(float* G, int ld, int n, int m, float* red) {
         const float inv = 1.f / pv;
         // swap rows k and p and scale the new row k (columns k .. W-1)
         for (int c = k + tid; c < W; c += kThreads) {
-            const float a = G[(size_t)k * ld + c];
-            const float b = G[(size_t)p * ld + c];
-            G[(size_t)p * ld + c] = a;
-            G[(size_t)k * ld + c] = b * inv;
+            const float a = G[k * ld + c];
+            const float b = G[p * ld + c];
+            G[p * ld + c] = a;
+            G[k * ld + c] = b * inv;
         }
         __syncthreads();
-        // eliminate column k from every other row (columns k+1 .. W-1); the
-        // flat index e = i wc + (c - k - 1) advances by kThreads per pass
+        // eliminate column k from every other row (columns k+1 .. W-1) in
+        // blocks of four rows: the flat index e = b wc + (c - k - 1) over
+        // row blocks b advances by kThreads per pass, and a pass issues all
+        // its reads (the pivot row's entry, the four multipliers in column
+        // k and the four entries) before its writes.  Column k and the
+        // pivot row are not written here, and each entry is read and
+        // written by one thread.
         const int wc = W - k - 1;
         if (wc > 0) {
-            int i = tid / wc, c = tid - i * wc;
-            const int di = kThreads / wc, dc = kThreads - di * wc;
-            for (; i < n;) {
-                if (i != k) G[(size_t)i * ld + k + 1 + c] -= G[(size_t)i * ld + k] * G[(size_t)k * ld + k + 1 + c];
-                i += di;
+            const int nb = (n + 3) / 4;
+            int b = tid / wc, c = tid - b * wc;
+            const int db = kThreads / wc, dc = kThreads - db * wc;
+            for (; b < nb;) {
+                const int col = k + 1 + c;
+                const float pk = G[k * ld + col];
+                float mv[4], gv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = 4 * b + q;
+                    const bool on = i < n && i != k;
+                    mv[q] = on ? G[i * ld + k] : 0.f;
+                    gv[q] = on ? G[i * ld + col] : 0.f;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = 4 * b + q;
+                    if (i < n && i != k) G[i * ld + col] = gv[q] - mv[q] * pk;
+                }
+                b += db;
                 c += dc;
-                if (c >= wc) { c -= wc; ++i; }
+                if (c >= wc) { c -= wc; ++b; }
             }
         }
         __syncthreads();
@@ -229,9 +339,15 @@ __device__ __forceinline__ size_t nn(const Args& a) { return (size_t)a.n * a.n; 
 __device__ __forceinline__ void flag(const Args& a, int b, bool ok) {
     if (!ok && threadIdx.x == 0) atomicMax(a.status + b, (int)CORD_ST_NOT_PD);
 }
-// the G matrix of this workgroup: LDS after the GEMM region, or its global slot
-__device__ __forceinline__ float* gbuf(const Args& a, float* lds, float* slot) {
-    return a.g_in_lds ? lds + kGemmLds : slot;
+// The solve matrix G of a workgroup lives in LDS after the GEMM region when
+// it fits, else in the workgroup's global slot.  The kernels run their body
+// once for each case (`with_g`), so that in the LDS case every access to G
+// is an LDS instruction (a pointer that may be either would make them all
+// generic ones, slower and with 64-bit addressing).
+template <class Body>
+__device__ __forceinline__ void with_g(const Args& a, float* lds, float* slot, Body body) {
+    if (a.g_in_lds) body(lds + kGemmLds);
+    else body(slot);
 }
 
 // ---------------------------------------------------------------- kernels
@@ -250,15 +366,16 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(Args a, int scan) {
     float* e = a.el[0] + ((size_t)b * (a.N + 1) + j + 1) * 3 * nn(a);
     wg_transpose(e, a.A + o, n);
     // Dt = (F F^T)^{-1}: solve [F F^T | I]
-    float* G = gbuf(a, lds, slot);
-    wg_copy(G, 2 * n, a.Rv + o, n, n, n, 1.f, 0.f);
-    for (int x = threadIdx.x; x < n * n; x += kThreads) {
-        const int r = x / n, c = x - r * n;
-        G[(size_t)r * 2 * n + n + c] = r == c ? 1.f : 0.f;
-    }
-    __syncthreads();
-    flag(a, b, wg_solve(G, 2 * n, n, n, lds + kGemmLds - 2 * kThreads));
-    wg_copy(e + nn(a), n, G + n, 2 * n, n, n, 1.f, 0.f);
+    with_g(a, lds, slot, [&](float* G) {
+        wg_copy(G, 2 * n, a.Rv + o, n, n, n, 1.f, 0.f);
+        for (int x = threadIdx.x; x < n * n; x += kThreads) {
+            const int r = x / n, c = x - r * n;
+            G[r * 2 * n + n + c] = r == c ? 1.f : 0.f;
+        }
+        __syncthreads();
+        flag(a, b, wg_solve(G, 2 * n, n, n, lds + kGemmLds - 2 * kThreads));
+        wg_copy(e + nn(a), n, G + n, 2 * n, n, n, 1.f, 0.f);
+    });
     wg_copy(e + 2 * nn(a), n, a.Qw + o, n, n, n, 1.f, 0.f);
     if (j == 0) {
         float* e0 = a.el[0] + (size_t)b * (a.N + 1) * 3 * nn(a);
@@ -270,18 +387,24 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(Args a, int scan) {
 
 // One Kalman step (eq. kalman_recursions, C = I) in the calling workgroup:
 // X = Pi A^T, [Rv + Pi | X] -> Y = (Rv + Pi)^{-1} X, L = -Y,
-// Pi' = Qw + A X - X^T Y.  `slot` holds X (n x n) and, when not in LDS, G.
-__device__ bool kalman_step(const Args& a, const float* A, const float* Qw, const float* Rv, const float* Pi,
-                            float* L, float* Pn, float* slot, float* lds) {
+// Pi' = Qw + A X - X^T Y.  `X` is n x n of the workgroup's slot, G the
+// solve matrix (n x 2n).
+__device__ __forceinline__ bool kalman_step(const Args& a, const float* A, const float* Qw, const float* Rv,
+                                            const float* Pi, float* L, float* Pn, float* X, float* G, float* lds) {
     const int n = a.n;
-    float* X = slot;
-    float* G = gbuf(a, lds, slot + nn(a));
     wg_gemm(X, n, Pi, n, false, A, n, true, n, n, n, 1.f, nullptr, 0, nullptr, 0, 0.f, lds);
-    for (int x = threadIdx.x; x < n * n; x += kThreads) {
-        const int r = x / n, c = x - r * n;
-        G[(size_t)r * 2 * n + c] = Rv[x] + Pi[x];
-        G[(size_t)r * 2 * n + n + c] = X[x];
-    }
+    wg_map(
+        n * n, [&](int x) { return Rv[x] + Pi[x]; },
+        [&](int x, float v) {
+            const int r = x / n, c = x - r * n;
+            G[(size_t)r * 2 * n + c] = v;
+        });
+    wg_map(
+        n * n, [&](int x) { return X[x]; },
+        [&](int x, float v) {
+            const int r = x / n, c = x - r * n;
+            G[(size_t)r * 2 * n + n + c] = v;
+        });
     __syncthreads();
     const bool ok = wg_solve(G, 2 * n, n, n, lds + kGemmLds - 2 * kThreads);
     if (L) wg_copy(L, n, G + n, 2 * n, n, n, -1.f, 0.f);
@@ -300,22 +423,30 @@ __device__ bool kalman_step(const Args& a, const float* A, const float* Qw, cons
 // matrices when the measurements are accurate (F F^T << Pi), which FP32
 // cannot resolve.  L = -(F F^T + Pi)^{-1} Pi A^T = W - A^T since
 // (I + Dinv Pi)^{-1} = (F F^T + Pi)^{-1} F F^T.)
-__device__ bool kalman_step_stable(const Args& a, const float* A, const float* Qw, const float* Dinv, const float* Pi,
-                                   float* L, float* Pn, float* slot, float* lds) {
+__device__ __forceinline__ bool kalman_step_stable(const Args& a, const float* A, const float* Qw, const float* Dinv,
+                                                   const float* Pi, float* L, float* Pn, float* X, float* G,
+                                                   float* lds) {
     const int n = a.n;
-    float* X = slot;
-    float* G = gbuf(a, lds, slot + nn(a));
     wg_gemm(G, 2 * n, Dinv, n, false, Pi, n, false, n, n, n, 1.f, nullptr, 0, nullptr, 0, 1.f, lds);
-    for (int x = threadIdx.x; x < n * n; x += kThreads) {
-        const int r = x / n, c = x - r * n;
-        G[(size_t)r * 2 * n + n + c] = A[(size_t)c * n + r];
-    }
+    wg_map(
+        n * n,
+        [&](int x) {
+            const int r = x / n, c = x - r * n;
+            return A[(size_t)c * n + r];
+        },
+        [&](int x, float v) {
+            const int r = x / n, c = x - r * n;
+            G[(size_t)r * 2 * n + n + c] = v;
+        });
     __syncthreads();
     const bool ok = wg_solve(G, 2 * n, n, n, lds + kGemmLds - 2 * kThreads);
-    for (int x = threadIdx.x; x < n * n; x += kThreads) {
-        const int r = x / n, c = x - r * n;
-        L[x] = G[(size_t)r * 2 * n + n + c] - A[(size_t)c * n + r];
-    }
+    wg_map(
+        n * n,
+        [&](int x) {
+            const int r = x / n, c = x - r * n;
+            return G[(size_t)r * 2 * n + n + c] - A[(size_t)c * n + r];
+        },
+        [&](int x, float v) { L[x] = v; });
     wg_gemm(X, n, Pi, n, false, A, n, true, n, n, n, 1.f, nullptr, 0, nullptr, 0, 0.f, lds);
     wg_gemm(Pn, n, G + n, 2 * n, true, X, n, false, n, n, n, 1.f, Qw, n, nullptr, 0, 0.f, lds);
     return ok;
@@ -332,12 +463,14 @@ __global__ __launch_bounds__(kThreads) void kalman_serial_kernel(Args a) {
     wg_gemm(Pi, n, a.Xi + (size_t)b * nn(a), n, false, a.Xi + (size_t)b * nn(a), n, true, n, n, n, 1.f, nullptr, 0,
             nullptr, 0, 0.f, lds);
     bool ok = true;
-    for (int j = 0; j < a.N; ++j) {
-        const size_t o = ((size_t)b * a.N + j) * nn(a);
-        const float* Dinv = el + (size_t)(j + 1) * 3 * nn(a) + nn(a);
-        ok &= kalman_step_stable(a, a.A + o, a.Qw + o, Dinv, Pi + j * nn(a), a.L + o, Pi + (j + 1) * nn(a), slot,
-                                 lds);
-    }
+    with_g(a, lds, slot + nn(a), [&](float* G) {
+        for (int j = 0; j < a.N; ++j) {
+            const size_t o = ((size_t)b * a.N + j) * nn(a);
+            const float* Dinv = el + (size_t)(j + 1) * 3 * nn(a) + nn(a);
+            ok &= kalman_step_stable(a, a.A + o, a.Qw + o, Dinv, Pi + j * nn(a), a.L + o, Pi + (j + 1) * nn(a), slot,
+                                     G, lds);
+        }
+    });
     flag(a, b, ok);
 }
 
@@ -348,7 +481,9 @@ __global__ __launch_bounds__(kThreads) void gains_kernel(Args a) {
     const size_t o = ((size_t)b * a.N + j) * nn(a);
     float* slot = a.ws + ((size_t)b * a.N + j) * a.ws_stride;
     const float* Pi = a.Pi + ((size_t)b * (a.N + 1) + j) * nn(a);
-    flag(a, b, kalman_step(a, a.A + o, nullptr, a.Rv + o, Pi, a.L + o, nullptr, slot, lds));
+    with_g(a, lds, slot + nn(a), [&](float* G) {
+        flag(a, b, kalman_step(a, a.A + o, nullptr, a.Rv + o, Pi, a.L + o, nullptr, slot, G, lds));
+    });
 }
 
 // grid (N+1, B): one round of the inclusive Hillis-Steele scan with offset
@@ -378,21 +513,22 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(Args a, int src, i
     const float* Pb = Ab + 2 * nn(a);
     float* slot = a.ws + ((size_t)b * (a.N + 1) + i) * a.ws_stride;
     float* T2 = slot;
-    float* G = gbuf(a, lds, slot + nn(a));
     const bool full = i >= 2 * off;
     const int m = full ? 2 * n : n;
     const int ld = n + m;
-    wg_gemm(G, ld, Db, n, false, Pa, n, false, n, n, n, 1.f, nullptr, 0, nullptr, 0, 1.f, lds);
-    wg_copy(G + n, ld, Ab, n, n, n, 1.f, 0.f);
-    if (full) wg_gemm(G + 2 * n, ld, Db, n, false, Aa, n, true, n, n, n, 1.f, nullptr, 0, nullptr, 0, 0.f, lds);
-    flag(a, b, wg_solve(G, ld, n, m, lds + kGemmLds - 2 * kThreads));
-    wg_gemm(T2, n, Pa, n, false, Ab, n, false, n, n, n, 1.f, nullptr, 0, nullptr, 0, 0.f, lds);
-    wg_gemm(Pout, n, G + n, ld, true, T2, n, false, n, n, n, 1.f, Pb, n, nullptr, 0, 0.f, lds);
-    if (full && !last) {
-        float* Ao = D + i * esz;
-        wg_gemm(Ao, n, Aa, n, false, G + n, ld, false, n, n, n, 1.f, nullptr, 0, nullptr, 0, 0.f, lds);
-        wg_gemm(Ao + nn(a), n, Aa, n, false, G + 2 * n, ld, false, n, n, n, 1.f, Da, n, nullptr, 0, 0.f, lds);
-    }
+    with_g(a, lds, slot + nn(a), [&](float* G) {
+        wg_gemm(G, ld, Db, n, false, Pa, n, false, n, n, n, 1.f, nullptr, 0, nullptr, 0, 1.f, lds);
+        wg_copy(G + n, ld, Ab, n, n, n, 1.f, 0.f);
+        if (full) wg_gemm(G + 2 * n, ld, Db, n, false, Aa, n, true, n, n, n, 1.f, nullptr, 0, nullptr, 0, 0.f, lds);
+        flag(a, b, wg_solve(G, ld, n, m, lds + kGemmLds - 2 * kThreads));
+        wg_gemm(T2, n, Pa, n, false, Ab, n, false, n, n, n, 1.f, nullptr, 0, nullptr, 0, 0.f, lds);
+        wg_gemm(Pout, n, G + n, ld, true, T2, n, false, n, n, n, 1.f, Pb, n, nullptr, 0, 0.f, lds);
+        if (full && !last) {
+            float* Ao = D + i * esz;
+            wg_gemm(Ao, n, Aa, n, false, G + n, ld, false, n, n, n, 1.f, nullptr, 0, nullptr, 0, 0.f, lds);
+            wg_gemm(Ao + nn(a), n, Aa, n, false, G + 2 * n, ld, false, n, n, n, 1.f, Da, n, nullptr, 0, 0.f, lds);
+        }
+    });
 }
 
 // ---------------------------------------------------------------- transitions
@@ -414,10 +550,13 @@ __global__ __launch_bounds__(kThreads) void ahat_kernel(TArgs t) {
     const int j = blockIdx.x, b = blockIdx.y, n = t.n;
     const size_t o = ((size_t)b * t.N + j) * n * n;
     if (!t.left) {
-        for (int e = threadIdx.x; e < n * n; e += kThreads) {
-            const int r = e / n, c = e - r * n;
-            t.Ahat[o + e] = t.A[o + e] + t.X[o + (size_t)c * n + r];
-        }
+        wg_map(
+            n * n,
+            [&](int e) {
+                const int r = e / n, c = e - r * n;
+                return t.A[o + e] + t.X[o + (size_t)c * n + r];
+            },
+            [&](int e, float v) { t.Ahat[o + e] = v; });
     } else {
         const float* K = t.X + ((size_t)b * (t.N + 1) + j) * t.m * n;
         wg_gemm(t.Ahat + o, n, t.Bm + ((size_t)b * t.N + j) * n * t.m, t.m, false, K, n, false, n, n, t.m, 1.f,
