@@ -831,7 +831,11 @@ struct Solver {
             pq = bsum(pq);
             ++cnt[1];
             if (!(pq > 0.f)) { ok = false; break; }
-            const float alpha = rz / pq;
+            // step lengths from the hardware reciprocal (1 ulp): two
+            // instructions instead of the ten of a correctly rounded
+            // division on the iteration's dependent chain; r and xs take
+            // the same alpha, so the recurrence stays consistent
+            const float alpha = rz * __builtin_amdgcn_rcpf(pq);
             float rzn = 0.f;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
@@ -842,7 +846,7 @@ struct Solver {
             }
             rzn = bsum(rzn);
             if (!(rzn > rtol * rtol * rz0)) break;
-            const float beta = rzn / rz;
+            const float beta = rzn * __builtin_amdgcn_rcpf(rz);
             rz = rzn;
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
