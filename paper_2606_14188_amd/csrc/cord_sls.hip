@@ -713,8 +713,28 @@ __global__ __launch_bounds__(kThreads) void tri_gemm128_kernel(int rows, int col
     const int ar = tid >> 1, ac = (tid & 1) * 8;
     const int br = tid >> 4, bc = (tid & 15) * 8;
     float ra_[8], rb_[8];
+    // A chunk that ends inside [k0, k1) needs no column test, and a thread
+    // whose A row and B columns are inside the tile needs no row or column
+    // test: those loads are unconditional (one branch per chunk); the last
+    // chunk and the edge threads take the element-wise tests.
+    const bool a_in = tm + ar < r1, b_in = tn + bc + 8 <= c1;
     auto load = [&](int kc) {
         const int gr = tm + ar;
+        const int gkb = kc + br;
+        if (kc + kBK <= k1 && a_in && b_in) {
+            const float* pa = Ab + (size_t)gr * K + kc + ac;
+            const float* pb = Bb + (size_t)gkb * cols + tn + bc;
+#pragma unroll
+            for (int q = 0; q < 8; q += 2) {
+                const float2 va = *reinterpret_cast<const float2*>(pa + q);
+                const float2 vb = *reinterpret_cast<const float2*>(pb + q);
+                ra_[q] = va.x;
+                ra_[q + 1] = va.y;
+                rb_[q] = vb.x;
+                rb_[q + 1] = vb.y;
+            }
+            return;
+        }
 #pragma unroll
         for (int q = 0; q < 8; q += 2) {
             const int gk = kc + ac + q;
@@ -724,13 +744,12 @@ __global__ __launch_bounds__(kThreads) void tri_gemm128_kernel(int rows, int col
             ra_[q] = v.x;
             ra_[q + 1] = v.y;
         }
-        const int gk = kc + br;
 #pragma unroll
         for (int q = 0; q < 8; q += 2) {
             const int gc = tn + bc + q;
             float2 v = make_float2(0.f, 0.f);
-            if (gk < k1 && gc + 1 < c1) v = *reinterpret_cast<const float2*>(Bb + (size_t)gk * cols + gc);
-            else if (gk < k1 && gc < c1) v.x = Bb[(size_t)gk * cols + gc];
+            if (gkb < k1 && gc + 1 < c1) v = *reinterpret_cast<const float2*>(Bb + (size_t)gkb * cols + gc);
+            else if (gkb < k1 && gc < c1) v.x = Bb[(size_t)gkb * cols + gc];
             rb_[q] = v.x;
             rb_[q + 1] = v.y;
         }
