@@ -8,7 +8,7 @@ import pytest
 
 import workloads as W
 from oracle.step import rollout as orollout
-from tests.parity import GRAD_TOL, STATE_TOL, check, gradient_block_errors, state_errors
+from tests.parity import GRAD_TOL, JAC_TOL, STATE_TOL, check, gradient_block_errors, state_errors, tangent_block_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -146,3 +146,56 @@ def test_c4_mixed_batch_graph():
     ta = alone.rollout(alone.pack_states([insts[j].s0]), alone.pack_controls([insts[j].u]))
     torch.cuda.synchronize()
     assert np.array_equal(alone.split(ta, "traj")[0], parts[j])
+
+
+def test_c4_largest_instances_sampled_steps():
+    """The largest cloth (48 x 48 nodes, T = 120) and the largest rope (256
+    nodes, T = 119) of the mixed batch, in its graph launch, over their
+    whole horizons: at sampled steps the oracle's step from the GPU's state
+    at t gives the GPU's state at t + 1, and the oracle's step derivative
+    applied to seeded tangents gives the GPU's JVP tangents there (the
+    per-step maps whose transposes the adjoint chains).  A whole-horizon
+    oracle rollout of the cloth would take it several minutes; the sampled
+    steps take seconds."""
+    import torch
+    from oracle.derivatives import StepDerivative
+    from oracle.step import split_state, step as ostep
+    from paper_2606_14188_amd import _lib as L
+    insts = W.config_c4()
+    big = [max((i for i in insts if i.kind == kind), key=lambda i: (i.n, i.T)) for kind in ("cloth", "rope")]
+    assert (big[0].n, big[0].T) == (2304, 120) and (big[1].n, big[1].T) == (256, 119)
+    sim, s0, u, _ = _setup(big)
+    sim.set_launch(L.LAUNCH_GRAPH)
+    st = torch.full((len(big),), -1, dtype=torch.int32, device=sim.device)
+    tr = sim.rollout(s0, u, status=st)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all(), st
+    parts = sim.split(tr, "traj")
+    k = 2
+    rng = np.random.default_rng(1031)
+    ds = [rng.normal(size=(i.T, k, i.n_s)) for i in big]
+    du = [rng.normal(size=(i.T, k, i.n_u)) for i in big]
+    st.fill_(-1)
+    _, _, jv = sim.linearize(tr, u, dense=False, want_B=False, jvp_k=k,
+                             jvp_ds=sim.pack_states([d.ravel() for d in ds]),
+                             jvp_du=sim.pack_states([d.ravel() for d in du]), status=st)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all(), st
+    h = jv.cpu().numpy()
+    off = 0
+    for j, inst in enumerate(big):
+        ns = inst.n_s
+        traj = parts[j].reshape(inst.T + 1, ns).astype(np.float64)
+        blk = h[off:off + inst.T * k * ns].reshape(inst.T, k, ns)
+        off += inst.T * k * ns
+        for t in (0, inst.T // 3, 2 * inst.T // 3, inst.T - 1):
+            print(f"{inst.kind} n={inst.n} T={inst.T} step {t}", flush=True)
+            x, v, _ = split_state(inst, traj[t])
+            r = ostep(inst, x, v, inst.u[t], inst.kappa_fwd)
+            assert r.status == 0
+            ex, ev = state_errors(traj[t + 1], np.concatenate([r.x.ravel(), r.v.ravel()]), inst.n)
+            print(f"  one step: x {ex:.2e} v {ev:.2e}", flush=True)
+            assert ex <= STATE_TOL and ev <= STATE_TOL
+            d = StepDerivative(inst, traj[t], inst.u[t], inst.kappa_bwd)
+            check(tangent_block_errors(blk[t], d.jvp_s(ds[j][t].T, du[j][t].T).T, inst.n), JAC_TOL,
+                  f"  {inst.kind} JVP at step {t}")
