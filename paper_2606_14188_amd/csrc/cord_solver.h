@@ -97,6 +97,23 @@ __device__ __forceinline__ void sym_inv(const float m[6], float o[6]) {
     o[0] = c00 * id; o[1] = c01 * id; o[2] = c02 * id;
     o[3] = c11 * id; o[4] = c12 * id; o[5] = c22 * id;
 }
+// entry (r, c) of a symmetric 3x3 stored as {a, b, c, d, e, f}
+__device__ __forceinline__ float sym_at(const float m[6], int r, int c) {
+    const int i = r <= c ? r : c, j = r <= c ? c : r;
+    return m[i == 0 ? j : i == 1 ? 2 + j : 5];
+}
+__device__ __forceinline__ void sym_to_full3(const float s[6], float m[3][3]) {
+    m[0][0] = s[0]; m[0][1] = s[1]; m[0][2] = s[2];
+    m[1][0] = s[1]; m[1][1] = s[3]; m[1][2] = s[4];
+    m[2][0] = s[2]; m[2][1] = s[4]; m[2][2] = s[5];
+}
+// positive definite by Sylvester's criterion
+__device__ __forceinline__ bool sym_pd(const float m[6]) {
+    const float m2 = m[0] * m[3] - m[1] * m[1];
+    const float m3 = m[0] * (m[3] * m[5] - m[4] * m[4]) - m[1] * (m[1] * m[5] - m[4] * m[2]) +
+                     m[2] * (m[1] * m[4] - m[3] * m[2]);
+    return m[0] > 0.f && m2 > 0.f && m3 > 0.f;
+}
 __device__ __forceinline__ void sym_mul(const float m[6], const float r[3], float o[3]) {
     o[0] = m[0] * r[0] + m[1] * r[1] + m[2] * r[2];
     o[1] = m[1] * r[0] + m[3] * r[1] + m[4] * r[2];
@@ -255,6 +272,10 @@ struct Solver {
     float x[PPT][3], v[PPT][3], d[PPT][3], dl[PPT][3], ug[PPT][3];
     float se[PPT][NS][3], sa[PPT][NS], sb[PPT][NS];
     float Bd[PPT][6], Mi[PPT][6];
+    // rope, one particle per lane: rows of the inverse of the 6 x 6 block of
+    // the particle pair (2q, 2q + 1) -- own columns (symmetric) and the
+    // partner's columns (row-major)
+    float Pd[PPT][6], Pc[PPT][9];
     float bw[PPT][3];       // rope: bending weights of the centres p-1, p, p+1 (zero if not a centre)
     float cn[PPT][NOBS][3], cphi[PPT][NOBS], clam[PPT][NOBS], cgap[PPT][NOBS];
     // friction (mu > 0; compiled only into the FRIC instantiation): the tangential
@@ -800,6 +821,107 @@ struct Solver {
 #pragma unroll
                 for (int i = 0; i < 6; ++i) Mi[k][i] = 0.f;
             }
+            if constexpr (kPairPrecond) {
+#pragma unroll
+                for (int i = 0; i < 6; ++i) mown[i] = m[i];
+            }
+        }
+        if constexpr (kPairPrecond) pair_precond(mown);
+    }
+
+    // Ropes with one particle per lane precondition the conjugate gradients
+    // with the inverse of the 6 x 6 diagonal block of each particle pair
+    // (2q, 2q + 1), held by adjacent lanes, instead of each particle's 3 x 3
+    // block: the pair's coupling (the spring between them and the bending
+    // weight) is the chain's stiffest off-diagonal term.  Both lanes of a
+    // pair form the same inverse from the same values (the even particle's
+    // coupling block, exchanged by DPP), so the preconditioner is exactly
+    // symmetric.  A pair with a particle that is not free, or whose block or
+    // Schur complement is not positive definite, keeps the 3 x 3 blocks.
+    static constexpr bool kPairPrecond = TOPO == kRope && PPT == 1;
+    float mown[6];
+    __device__ __forceinline__ void pair_precond(const float own[6]) {
+        const int p = pidx(0);
+        const bool even = (p & 1) == 0;
+        // coupling of p and p + 1 as the even particle sees it:
+        // -(sa e e^T + sb I) of the spring between them + the bending weight
+        float c6[6];
+        {
+            const float cb = bw[0][1] - 2.f * bw[0][2];
+            const float a = sa[0][0], b = sb[0][0];
+            const float* e = se[0][0];
+            c6[0] = cb - (a * e[0] * e[0] + b);
+            c6[1] = -a * e[0] * e[1];
+            c6[2] = -a * e[0] * e[2];
+            c6[3] = cb - (a * e[1] * e[1] + b);
+            c6[4] = -a * e[1] * e[2];
+            c6[5] = cb - (a * e[2] * e[2] + b);
+        }
+        float A[6], B[6], C[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const float op = dpp_mov<0xB1>(own[i]), cp = dpp_mov<0xB1>(c6[i]);
+            A[i] = even ? own[i] : op;
+            B[i] = even ? op : own[i];
+            C[i] = even ? c6[i] : cp;
+        }
+        const float fp = dpp_mov<0xB1>(isfree(0) ? 1.f : 0.f);
+        float Cf[3][3], Ai[6], X[3][3], S[6], Si[6];
+        sym_to_full3(C, Cf);
+        sym_inv(A, Ai);
+        // X = A^{-1} C
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                X[r][c] = sym_at(Ai, r, 0) * Cf[0][c] + sym_at(Ai, r, 1) * Cf[1][c] + sym_at(Ai, r, 2) * Cf[2][c];
+        // S = B - C^T X (upper triangle)
+        {
+            int q = 0;
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = r; c < 3; ++c, ++q)
+                    S[q] = B[q] - (Cf[0][r] * X[0][c] + Cf[1][r] * X[1][c] + Cf[2][r] * X[2][c]);
+        }
+        const bool ok = isfree(0) && fp > 0.f && sym_pd(A) && sym_pd(S);
+        sym_inv(S, Si);
+        // P12 = -X S^{-1};  P11 = A^{-1} - P12 X^T;  P22 = S^{-1}
+        float P12[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                P12[r][c] = -(X[r][0] * sym_at(Si, 0, c) + X[r][1] * sym_at(Si, 1, c) + X[r][2] * sym_at(Si, 2, c));
+        float P11[6];
+        {
+            int q = 0;
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = r; c < 3; ++c, ++q)
+                    P11[q] = Ai[q] - (P12[r][0] * X[c][0] + P12[r][1] * X[c][1] + P12[r][2] * X[c][2]);
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) Pd[0][i] = ok ? (even ? P11[i] : Si[i]) : Mi[0][i];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Pc[0][3 * r + c] = ok ? (even ? P12[r][c] : P12[c][r]) : 0.f;
+    }
+
+    // z = M^{-1} r: the pair blocks on ropes with one particle per lane,
+    // else the 3 x 3 blocks.  Every lane of the workgroup must execute it
+    // (the partner's residual is read by DPP).
+    __device__ __forceinline__ void precond(const float r[PPT][3], float z[PPT][3]) const {
+        if constexpr (kPairPrecond) {
+            const float q0 = dpp_mov<0xB1>(r[0][0]), q1 = dpp_mov<0xB1>(r[0][1]), q2 = dpp_mov<0xB1>(r[0][2]);
+            sym_mul(Pd[0], r[0], z[0]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) z[0][c] += Pc[0][3 * c] * q0 + Pc[0][3 * c + 1] * q1 + Pc[0][3 * c + 2] * q2;
+        } else {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) sym_mul(Mi[k], r[k], z[k]);
         }
     }
 
@@ -810,10 +932,12 @@ struct Solver {
         float r[PPT][3], z[PPT][3], pp[PPT][3], q[PPT][3];
         float rz = 0.f;
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
+        for (int k = 0; k < PPT; ++k)
 #pragma unroll
             for (int c = 0; c < 3; ++c) { xs[k][c] = 0.f; r[k][c] = isfree(k) ? b[k][c] : 0.f; }
-            sym_mul(Mi[k], r[k], z[k]);
+        precond(r, z);
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) pp[k][c] = z[k][c];
             rz += dot3(r[k], z[k]);
@@ -838,12 +962,12 @@ struct Solver {
             const float alpha = rz * __builtin_amdgcn_rcpf(pq);
             float rzn = 0.f;
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
+            for (int k = 0; k < PPT; ++k)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { xs[k][c] += alpha * pp[k][c]; r[k][c] -= alpha * q[k][c]; }
-                sym_mul(Mi[k], r[k], z[k]);
-                rzn += dot3(r[k], z[k]);
-            }
+            precond(r, z);
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) rzn += dot3(r[k], z[k]);
             rzn = bsum(rzn);
             if (!(rzn > rtol * rtol * rz0)) break;
             const float beta = rzn * __builtin_amdgcn_rcpf(rz);
