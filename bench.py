@@ -36,9 +36,11 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
 # per conjugate-gradient iteration,
 # per Newton iteration (gradient + Hessian data + preconditioner + line
 # search), per interior-point iteration (residuals, right-hand side, step
-# rule) and per solved step (predictor, contacts, output).
+# rule) and per solved step (predictor, contacts, output).  Ropes with one
+# particle per lane apply and build the pair-block preconditioner: 18 more
+# per iteration, about 250 more per build (Newton and interior point).
 FLOPS_PER_PARTICLE = {
-    "rope": {"pcg": 135.0, "newton": 350.0, "ipm": 400.0, "step": 150.0},
+    "rope": {"pcg": 153.0, "newton": 600.0, "ipm": 650.0, "step": 150.0},
     "cloth": {"pcg": 300.0, "newton": 900.0, "ipm": 500.0, "step": 150.0},
 }
 
