@@ -82,7 +82,8 @@ def _dev(d):
     return {k: torch.from_numpy(v).cuda() for k, v in d.items()}
 
 
-@pytest.mark.parametrize("B,N,n,m", [(2, 7, 10, 3), (2, 5, 70, 6), (1, 3, 110, 4), (3, 1, 9, 2), (1, 15, 12, 3)])
+@pytest.mark.parametrize("B,N,n,m", [(2, 7, 10, 3), (2, 5, 70, 6), (1, 3, 110, 4), (3, 1, 9, 2), (1, 15, 12, 3),
+                                     (2, 4, 1, 1), (1, 2, 130, 5)])
 def test_sls_stage3_matches_oracle(B, N, n, m):
     import torch
     from paper_2606_14188_amd.sls import SCAN, SERIAL, SLS
